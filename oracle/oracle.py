@@ -1,0 +1,169 @@
+"""ctypes front end of the FP64 oracle (test infrastructure only).
+
+The numerics live in ``qdvm_oracle.c`` (direct summation, no transforms).  This
+module only compiles it with gcc, marshals numpy arrays and picks the
+parameters the paper fixes:
+
+* lines through 0 of the box [-order, order]^d, one primitive representative
+  per line with its first nonzero component positive (Sec. 3.2, Farey series
+  and the set A^{d-1}), listed by (|e|_inf, |e|_2^2, lexicographic);
+* default weights a(k) = h^(2d-1) |k| / gcd(k), b = 1 (Sec. 3.2, after
+  eq. (3.3)), which is h^(2d-1) |e_p|_2 on the line of e_p;
+* default truncation Nt = floor(n / (3 + sqrt 2)) (Sec. 4, the choice of Nt
+  next to Table 1; the printed values 1, 3, 7, 14 for 8, 16, 32, 64 points).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qdvm_oracle.c")
+_LIBDIR = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_LIBDIR, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
+    os.makedirs(_LIBDIR, exist_ok=True)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_lines.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int]
+        lib.oracle_lines.restype = ctypes.c_int
+        lib.oracle_default_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, i32p, dp]
+        lib.oracle_collide.argtypes = [ctypes.c_int] * 4 + [i32p, dp, ctypes.c_int, dp, dp]
+        lib.oracle_collide_terms.argtypes = [ctypes.c_int] * 4 + [i32p, dp, dp]
+        lib.oracle_vjp.argtypes = [ctypes.c_int] * 4 + [i32p, dp, ctypes.c_int, dp, dp, dp, dp]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        _lib = lib
+        return lib
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lines(d: int, order: int) -> np.ndarray:
+    """All lines of the box [-order, order]^d, canonical representatives, (count, d)."""
+    lib = _load()
+    cnt = lib.oracle_lines(d, order, None, 0)
+    if cnt < 0:
+        raise ValueError("bad dimension or order")
+    out = np.zeros((cnt, d), dtype=np.int32)
+    _, ptr = _i32(out)
+    lib.oracle_lines(d, order, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cnt)
+    return out
+
+
+def first_lines(d: int, count: int) -> np.ndarray:
+    """The first `count` lines in canonical order."""
+    order = 1
+    while True:
+        ls = lines(d, order)
+        if len(ls) >= count:
+            # every line of a larger order has a larger |e|_inf, so the prefix is stable
+            return ls[:count].copy()
+        order += 1
+
+
+def default_weights(d: int, h: float, dirs) -> np.ndarray:
+    lib = _load()
+    dirs, dptr = _i32(dirs)
+    w = np.zeros(len(dirs), dtype=np.float64)
+    lib.oracle_default_weights(d, float(h), len(dirs), dptr,
+                               w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return w
+
+
+def default_ntilde(n: int) -> int:
+    return int(math.floor(n / (3.0 + math.sqrt(2.0))))
+
+
+def _cells(f, d, n):
+    f = np.asarray(f, dtype=np.float64)
+    npts = n ** d
+    if f.size % npts:
+        raise ValueError("f size is not a multiple of n^d")
+    return np.ascontiguousarray(f), f.size // npts
+
+
+def collide(d, n, ntilde, dirs, w, f) -> np.ndarray:
+    """Q(f, f) by direct summation; f has shape (..., n, ..., n) or (batch*n^d,)."""
+    lib = _load()
+    f, batch = _cells(f, d, n)
+    dirs, dptr = _i32(dirs)
+    w, wptr = _f64(w)
+    q = np.zeros_like(f)
+    lib.oracle_collide(d, n, ntilde, len(dirs), dptr, wptr, batch,
+                       f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return q
+
+
+def collide_terms(d, n, ntilde, dirs, f) -> np.ndarray:
+    """Unit-weight per-direction contributions Q_p for one cell, shape (P, n^d)."""
+    lib = _load()
+    f, batch = _cells(f, d, n)
+    if batch != 1:
+        raise ValueError("collide_terms takes one cell")
+    dirs, dptr = _i32(dirs)
+    out = np.zeros((len(dirs), n ** d), dtype=np.float64)
+    lib.oracle_collide_terms(d, n, ntilde, len(dirs), dptr,
+                             f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def vjp(d, n, ntilde, dirs, w, f, c):
+    """(grad_f, grad_w) of <c, Q(f; w)>; grad_w summed over cells."""
+    lib = _load()
+    f, batch = _cells(f, d, n)
+    c, batch_c = _cells(c, d, n)
+    if batch_c != batch:
+        raise ValueError("f and c differ in size")
+    dirs, dptr = _i32(dirs)
+    w, wptr = _f64(w)
+    gf = np.zeros_like(f)
+    gw = np.zeros(len(dirs), dtype=np.float64)
+    P = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_vjp(d, n, ntilde, len(dirs), dptr, wptr, batch, f.ctypes.data_as(P),
+                   c.ctypes.data_as(P), gf.ctypes.data_as(P), gw.ctypes.data_as(P))
+    return gf, gw
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    _load().oracle_set_num_threads(int(t))
