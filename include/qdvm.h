@@ -1,0 +1,151 @@
+/*
+ * qdvm.h -- C interface of the MI355X (gfx950) implementation of the fast
+ * discrete-velocity (DVM) Boltzmann collision operator of
+ *   C. Mouhot, L. Pareschi, T. Rey, "Convolutive decomposition and fast
+ *   summation methods for discrete-velocity approximations of the Boltzmann
+ *   equation".
+ *
+ * The operator (Sec. 2.3, eq. (2.9), restricted by the direction decomposition
+ * of Sec. 3.2, eqs. (3.6)-(3.7), with the decoupled weights a(k) b(l) of
+ * eq. (3.3), b = 1 and a constant on each lattice line):
+ *
+ *   Q_i = sum_p w_p sum_{0<|m|<=M_p} sum_{l.e_p=0, |l|_inf<=Nt}
+ *              [ f(i + m e_p) f(i + l) - f(i) f(i + m e_p + l) ],
+ *   M_p = floor(Nt / |e_p|_inf),
+ *
+ * on the periodic grid (Z/nZ)^d with n points per axis.  It is evaluated by
+ * FFT convolutions (Sec. 3.3) at O(P n^d log n) cost.
+ *
+ * Conventions common to every call
+ *   - A cell is one distribution function f on the n^d grid, FP32, C order
+ *     (last axis fastest), point j at velocity v_j = -R + j h, h = 2R/n.
+ *     The grid origin does not enter Q; only moments need the velocities.
+ *   - Array arguments named "device" are device pointers owned by the caller;
+ *     "host" arguments are host pointers read during the call only.
+ *   - Launches are asynchronous on the given HIP stream (NULL = the legacy
+ *     default stream).  Errors detected on the host are returned at once and
+ *     nothing is launched or written; faults inside kernels surface as
+ *     QDVM_EDEVICE from a later synchronising call.
+ *   - A plan's device workspace is shared by all calls on that plan: calls on
+ *     one plan must be ordered (one stream, or externally serialised).
+ *     Different plans are independent.  Plans are bound to the device that
+ *     was current at creation; calls must be made with that device current.
+ *   - No exception crosses this interface.
+ */
+#ifndef QDVM_H
+#define QDVM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QDVM_ABI_VERSION 1
+
+typedef enum {
+    QDVM_OK = 0,
+    QDVM_EINVAL = -1,        /* invalid argument (null pointer, bad size, bad direction...) */
+    QDVM_EUNSUPPORTED = -2,  /* valid request this build does not implement (grid size) */
+    QDVM_ENOMEM = -3,        /* device allocation failed */
+    QDVM_EDEVICE = -4        /* HIP runtime or kernel failure */
+} qdvm_status;
+
+typedef struct qdvm_plan_s* qdvm_plan_t;   /* opaque, immutable after creation */
+
+/*
+ * Plan descriptor: the parameters of Sec. 3.3 (n, the truncation Nt through
+ * the box, the direction set through Nbar) and the weights of Sec. 3.2.
+ */
+typedef struct {
+    int32_t dim;            /* d in {2, 3} */
+    int32_t n;              /* points per axis; supported: 2D {8,16,32,64}, 3D {8,16,24,32} */
+    double half_width;      /* R > 0: the grid spans [-R, R)^d, h = 2R/n */
+    int32_t ntilde;         /* Nt; 0 selects floor(n / (3 + sqrt 2)) (Sec. 4).  Requires
+                               1 <= Nt and 2 Nt + 1 <= n */
+    int32_t farey_order;    /* Nbar >= 1: use every line of [-Nbar, Nbar]^d (Sec. 3.2, the set
+                               A^{d-1}); used when dirs == NULL and num_dirs == 0 */
+    int32_t num_dirs;       /* P > 0 with dirs == NULL: the first P lines in canonical order
+                               (|e|_inf, then |e|_2^2, then components ascending) */
+    const int32_t* dirs;    /* optional host array P x d: primitive vectors, first nonzero
+                               component positive, no two on the same line */
+    const double* weights;  /* optional host array of P weights; NULL selects
+                               a(k) = h^(2d-1) |e_p|_2 (Sec. 3.2, after eq. (3.3)) */
+} qdvm_desc;
+
+typedef struct {
+    int32_t dim, n, ntilde;
+    int32_t num_dirs;       /* P */
+    int32_t num_jobs;       /* inverse transforms per cell in the direction loop */
+    double h;
+} qdvm_plan_info_t;
+
+/* Build a plan: direction set, line lengths M_p, weights and FP64-built
+ * multiplier tables, uploaded to the current device.  *out is written only on
+ * success.  EINVAL for an invalid descriptor, EUNSUPPORTED for n outside the
+ * supported set, ENOMEM/EDEVICE for device failures. */
+qdvm_status qdvm_plan(const qdvm_desc* desc, qdvm_plan_t* out);
+
+/* Destroy a plan.  Synchronises the device (work on any stream may still read
+ * the plan), then frees its device memory.  NULL is accepted (no-op). */
+qdvm_status qdvm_plan_destroy(qdvm_plan_t plan);
+
+/* Host-only preview of the direction set a descriptor selects (no device
+ * work): *num_dirs receives P; up to `cap` lines are written to dirs_out
+ * (host, cap x d int32), weights_out (host, cap doubles) and line_len_out
+ * (host, cap int32: M_p); any output may be NULL.  Same validation as
+ * qdvm_plan. */
+qdvm_status qdvm_describe(const qdvm_desc* desc, int32_t* num_dirs, int32_t* dirs_out, double* weights_out,
+                          int32_t* line_len_out, int32_t cap);
+
+/* Plan parameters (host struct written on success). */
+qdvm_status qdvm_plan_info(qdvm_plan_t plan, qdvm_plan_info_t* info);
+
+/* Direction set of a plan: dirs_out (host, P x d int32), weights_out (host,
+ * P doubles: the default or descriptor weights), line_len_out (host, P int32:
+ * M_p).  Any output may be NULL. */
+qdvm_status qdvm_plan_dirs(qdvm_plan_t plan, int32_t* dirs_out, double* weights_out, int32_t* line_len_out);
+
+/*
+ * Evaluate Q(f, f) for `batch` cells that share the plan.
+ *   f  device, batch * n^d floats, cells back to back.
+ *   q  device, batch * n^d floats: q = Q(f) when dt == 0, else the forward
+ *      Euler update q = f + dt Q(f) (Prop. 3.3, eq. (3.8)).  q may equal f
+ *      (in place); partial overlap is not allowed.
+ *   w  optional device array of P FP32 weights overriding the plan's for
+ *      this call only (the plan is never modified); NULL uses the plan's.
+ * batch == 0 is a no-op.  Inputs with NaN/Inf propagate into the output.
+ */
+qdvm_status qdvm_eval(qdvm_plan_t plan, int32_t batch, const float* f, float* q, const float* w,
+                      float dt, hipStream_t stream);
+
+/*
+ * Vector-Jacobian product of Q with respect to f and the weights, for `batch`
+ * cells sharing the plan, with cotangent `cot`:
+ *   grad_f  device, batch * n^d floats, overwritten: d<cot, Q>/df per cell.
+ *           Must not overlap f or cot.
+ *   grad_w  optional device array of P floats, overwritten: d<cot, Q>/dw_p
+ *           summed over the batch in a fixed order (deterministic).  A
+ *           direction with M_p = 0 gets 0.
+ *   w       optional device weights as in qdvm_eval.
+ */
+qdvm_status qdvm_vjp(qdvm_plan_t plan, int32_t batch, const float* f, const float* cot, const float* w,
+                     float* grad_f, float* grad_w, hipStream_t stream);
+
+/* Kernel variant (FFT radix order) used by eval (op 0) and vjp (op 1):
+ * -1 restores automatic choice.  qdvm_autotune times every variant on
+ * `batch` synthetic cells on `stream` and keeps the fastest per op. */
+qdvm_status qdvm_set_variant(qdvm_plan_t plan, int32_t op, int32_t variant);
+qdvm_status qdvm_get_variant(qdvm_plan_t plan, int32_t op, int32_t* variant);
+qdvm_status qdvm_autotune(qdvm_plan_t plan, int32_t batch, hipStream_t stream);
+
+const char* qdvm_status_string(qdvm_status status);
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* qdvm_last_error(void);
+int32_t qdvm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QDVM_H */

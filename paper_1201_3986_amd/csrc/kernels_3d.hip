@@ -1,0 +1,553 @@
+// HIP kernels (gfx950) of the fast DVM collision operator: 3D cells, the
+// multiplier preparation, the grad_w reduction and the launch dispatch.
+//
+// Mouhot, Pareschi, Rey, Sec. 3.2: under the decoupling (3.3), the kernel modes
+// split over lattice directions (3.6), and each direction of the operator
+// (3.7) is a pair of convolutions of f -- along the line e_p Z (multiplier
+// alpha_p) and over the plane e_p^perp (multiplier alpha'_p) -- multiplied
+// pointwise, minus f times the convolution with alpha_p alpha'_p (the loss).
+// Both multipliers are real and even, so one complex inverse transform of
+// (alpha_p + i alpha'_p) fhat yields the line sum g_p in its real part and the
+// plane sum h_p in its imaginary part; the losses of all directions are one
+// transform of Lambda fhat with Lambda = sum_p w_p alpha_p alpha'_p:
+//
+//     Q = sum_p w_p g_p h_p - f * IFFT(Lambda fhat).
+//
+// Execution model.  A lane owns whole pencils (1-D lines of the grid) in
+// VGPRs and transforms them with the unrolled in-register FFT; passing from
+// one axis to the next is a transpose through LDS, real and imaginary parts in
+// turn so the staging buffer is only n^d floats.  The spectrum of f is kept in
+// a per-slot global scratch (L2 resident) and re-read for each direction.
+//   2D (n <= 64): one lane per pencil, a cell is n lanes of one wave, the
+//                 transposes never leave the wave.
+//   3D: one cell per workgroup of T threads, each lane owns Q = n^2/T
+//       pencils; transposes are workgroup-wide.
+// Unnormalised transforms are used throughout; the 1/n^d factors are folded
+// into the prepared job weights (W_j / n^{2d}) and into Lambda (/ n^d).
+#include "kernels_common.h"
+
+namespace qdvm {
+
+// ------------------------------------------------------------------ 3D cell
+// Pencil phases (element index e runs along the pencil):
+//   X: pencil pi = y*n + z, e = x      (real space; coalesced I/O at x*n^2 + pi)
+//   Y: pencil pi = x*n + z, e = y
+//   Z: pencil pi = x*n + y, e = z      (spectral; scratch/tables at Kz*n^2 + pi)
+// LDS address of (x, y, z): x*SX + y*(n+1) + z, SX = n*(n+1).
+template <int N, int PH>
+__device__ __forceinline__ int addr3(int pi, int e)
+{
+    constexpr int SY = N + 1, SX = N * (N + 1);
+    const int a = pi / N, b = pi % N;
+    if (PH == 0) return e * SX + a * SY + b;
+    if (PH == 1) return a * SX + e * SY + b;
+    return a * SX + b * SY + e;
+}
+
+template <int N, int T, int Q, int PA, int PB>
+__device__ __forceinline__ void block_transpose(float2 (&z)[Q][N], float* xb, int tid)
+{
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < N; ++e) xb[addr3<N, PA>(tid + q * T, e)] = part ? z[q][e].y : z[q][e].x;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const float v = xb[addr3<N, PB>(tid + q * T, e)];
+                if (part) z[q][e].y = v;
+                else z[q][e].x = v;
+            }
+    }
+}
+
+template <int N, int T, int Q, int RV>
+__device__ __forceinline__ void fwd3d(float2 (&z)[Q][N], float* xb, int tid)
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, -1>(z[q]);
+    block_transpose<N, T, Q, 0, 1>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, -1>(z[q]);
+    block_transpose<N, T, Q, 1, 2>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, -1>(z[q]);
+}
+
+template <int N, int T, int Q, int RV>
+__device__ __forceinline__ void inv3d(float2 (&z)[Q][N], float* xb, int tid)
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
+    block_transpose<N, T, Q, 2, 1>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
+    block_transpose<N, T, Q, 1, 0>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
+}
+
+template <int N, int T, int Q>
+__device__ __forceinline__ float block_sum(float v, float* red, int tid)
+{
+    v = group_sum<64>(v);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < (T + 63) / 64; ++w) t += red[w];
+    return t;
+}
+
+// Buffers of one 3D cell: lane pencil pi = tid + q*T, element e at pi + e*n^2.
+struct Cell3D {
+    rsrc_t f, q, fh;
+};
+
+template <int N, int T, int RV>
+__device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl, rsrc_t rlam,
+                                            const float* __restrict__ jobw, float dt, float* xb,
+                                            const float* dtab, int tid)
+{
+    constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
+    float2 z[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
+            const float l = bload(rlam, (tid + q * T) * 4, k * RS);
+            z[q][k].x *= l;
+            z[q][k].y *= l;
+            QDVM_CHUNK_FENCE(k);
+        }
+    inv3d<N, T, Q, RV>(z, xb, tid);
+    float acc[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) acc[q][x] = -bload(cl.f, (tid + q * T) * 4, x * RS) * z[q][x].x;
+
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const float cw = jobw[jb];
+        const float* D = dtab + J.M * N;
+        const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+        const int ds = modc<N>(J.e[2]);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
+                z[q][k] = make_float2(al * F.x - a2 * F.y, al * F.y + a2 * F.x);
+                sidx += ds;
+                sidx -= (sidx >= N) ? N : 0;
+                QDVM_CHUNK_FENCE(k);
+            }
+        }
+        inv3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) acc[q][x] = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, acc[q][x]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+            const int v = (tid + q * T) * 4;
+            bstore(dt == 0.f ? acc[q][x] : __builtin_fmaf(dt, acc[q][x], bload(cl.f, v, x * RS)), cl.q, v, x * RS);
+        }
+}
+
+// Adjoint of one cell.  With c the cotangent and unnormalised transforms F:
+//   l + i C(cf) = IFFT(Lambda (fhat + i F(cf)))            (both real)
+//   per job:  u + i v = IFFT((a + i a') fhat) = n^d (g + i h)
+//             dQ/dw_j part: <c, g h> - <cf, l_j>, the second term by Parseval:
+//             n^{-2d} sum_x c u v - n^{-d} sum_K a a' Re(conj(F(cf)) fhat)
+//             S += W_j / n^{2d} (a - i a') F(c v + i c u)
+//   grad_f = Re IFFT(S) - c l - C(cf)
+// which uses A(c h) + B(c g) = Re IFFT((a - i a') F(c h + i c g)), valid because
+// the multipliers a = alpha_j and a' = alpha'_j are real and even.
+template <int N, int T, int RV>
+__device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, rsrc_t rc, rsrc_t rch,
+                                           rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
+                                           float* __restrict__ gwp, float inv_n2, float inv_n, float* xb,
+                                           float* red, const float* dtab, int tid)
+{
+    constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
+    float2 z[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < N; ++k) bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+            const int v = (tid + q * T) * 4;
+            z[q][x] = make_float2(bload(rc, v, x * RS) * bload(cl.f, v, x * RS), 0.f);
+            QDVM_CHUNK_FENCE(x);
+        }
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const int pi = tid + q * T;
+            bstore2(z[q][k], rch, pi * 8, k * RS2);
+            const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+            const float l = bload(rlam, pi * 4, k * RS);
+            z[q][k] = make_float2(l * (F.x - z[q][k].y), l * (F.y + z[q][k].x));
+            QDVM_CHUNK_FENCE(k);
+        }
+    inv3d<N, T, Q, RV>(z, xb, tid);
+    float acc[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) acc[q][x] = -bload(rc, (tid + q * T) * 4, x * RS) * z[q][x].x - z[q][x].y;
+
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const float cw = jobw[jb];
+        const float* D = dtab + J.M * N;
+        const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+        const int ds = modc<N>(J.e[2]);
+        float spart = 0.f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+                const float2 C = bload2(rch, pi * 8, k * RS2);
+                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
+                z[q][k] = make_float2(al * F.x - a2 * F.y, al * F.y + a2 * F.x);
+                spart = __builtin_fmaf(al * a2, C.x * F.x + C.y * F.y, spart);
+                sidx += ds;
+                sidx -= (sidx >= N) ? N : 0;
+                QDVM_CHUNK_FENCE(k);
+            }
+        }
+        inv3d<N, T, Q, RV>(z, xb, tid);
+        float rpart = 0.f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) {
+                const float c = bload(rc, (tid + q * T) * 4, x * RS);
+                rpart = __builtin_fmaf(c * z[q][x].x, z[q][x].y, rpart);
+                z[q][x] = make_float2(c * z[q][x].y, c * z[q][x].x);
+                QDVM_CHUNK_FENCE(x);
+            }
+        const float tot = block_sum<N, T, Q>(rpart * inv_n2 - spart * inv_n, red, tid);
+        if (tid == 0) gwp[jb] = tot;
+        fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
+                float2 t = make_float2(cw * (al * z[q][k].x + a2 * z[q][k].y),
+                                       cw * (al * z[q][k].y - a2 * z[q][k].x));
+                if (jb > 0) {
+                    const float2 sv = bload2(rsh, pi * 8, k * RS2);
+                    t.x += sv.x;
+                    t.y += sv.y;
+                }
+                bstore2(t, rsh, pi * 8, k * RS2);
+                sidx += ds;
+                sidx -= (sidx >= N) ? N : 0;
+                QDVM_CHUNK_FENCE(k);
+            }
+        }
+    }
+    if (pl.njobs > 0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int k = 0; k < N; ++k) z[q][k] = bload2(rsh, (tid + q * T) * 8, k * RS2);
+        inv3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) acc[q][x] += z[q][x].x;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) bstore(acc[q][x], cl.q, (tid + q * T) * 4, x * RS);
+}
+
+template <int N, int T, int RV>
+__global__ __launch_bounds__(T) void k_eval3d(DevPlan pl, int batch, const float* f, float* q, float dt,
+                                              DevScratch s)
+{
+    constexpr int NN = N * N, NPTS = NN * N;
+    extern __shared__ float smem[];
+    float* xb = smem;
+    float* dtab = smem + N * N * (N + 1);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < (pl.ntilde + 1) * N; i += T) dtab[i] = pl.dirichlet[i];
+    __syncthreads();
+    const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
+    Cell3D cl;
+    cl.fh = make_rsrc(s.spec + (size_t)blockIdx.x * NPTS, NPTS * 8);
+    for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
+        cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
+        cl.q = make_rsrc(q + (size_t)cell * NPTS, NPTS * 4);
+        cell3d_eval<N, T, RV>(pl, cl, rlam, s.jobw, dt, xb, dtab, tid);
+    }
+}
+
+template <int N, int T, int RV>
+__global__ __launch_bounds__(T) void k_vjp3d(DevPlan pl, int batch, const float* __restrict__ f,
+                                             const float* __restrict__ c, float* __restrict__ g,
+                                             DevScratch s)
+{
+    constexpr int NN = N * N, NPTS = NN * N;
+    extern __shared__ float smem[];
+    float* xb = smem;
+    float* dtab = smem + N * N * (N + 1);
+    float* red = dtab + (pl.ntilde + 1) * N;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < (pl.ntilde + 1) * N; i += T) dtab[i] = pl.dirichlet[i];
+    __syncthreads();
+    const size_t slot = (size_t)blockIdx.x * NPTS;
+    const float inv_n = 1.f / (float)NPTS;
+    const float inv_n2 = inv_n * inv_n;
+    const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
+    const rsrc_t rch = make_rsrc(s.spec2 + slot, NPTS * 8);
+    const rsrc_t rsh = make_rsrc(s.acc + slot, NPTS * 8);
+    Cell3D cl;
+    cl.fh = make_rsrc(s.spec + slot, NPTS * 8);
+    for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
+        cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
+        cl.q = make_rsrc(g + (size_t)cell * NPTS, NPTS * 4);
+        const rsrc_t rc = make_rsrc(c + (size_t)cell * NPTS, NPTS * 4);
+        cell3d_vjp<N, T, RV>(pl, cl, rc, rch, rsh, rlam, s.jobw, s.gw_part + (size_t)cell * pl.njobs, inv_n2,
+                             inv_n, xb, red, dtab, tid);
+    }
+}
+
+// ------------------------------------------------------------------ prep
+// Lambda/n^d at every spectral index and the job weights W_j / n^{2d}, from the
+// per-direction weights w (W_j = w_p + w_pp for a 2D perpendicular pair).
+__global__ void k_prep(DevPlan pl, const float* __restrict__ w, float* __restrict__ lam,
+                       float* __restrict__ jobw)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = pl.n, npts = pl.npts;
+    const double inv = 1.0 / (double)npts;
+    if (idx < pl.njobs) {
+        const JobDesc J = pl.jobs[idx];
+        const double W = (double)w[J.p] + (J.pp >= 0 ? (double)w[J.pp] : 0.0);
+        jobw[idx] = (float)(W * inv * inv);
+    }
+    if (idx >= npts) return;
+    int K[3];
+    if (pl.dim == 2) {
+        K[1] = idx / n;
+        K[0] = idx % n;
+        K[2] = 0;
+    } else {
+        K[2] = idx / (n * n);
+        const int pi = idx % (n * n);
+        K[0] = pi / n;
+        K[1] = pi % n;
+    }
+    double acc = 0.0;
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const double W = (double)w[J.p] + (J.pp >= 0 ? (double)w[J.pp] : 0.0);
+        int sd = J.e[0] * K[0] + J.e[1] * K[1] + J.e[2] * K[2];
+        sd %= n;
+        if (sd < 0) sd += n;
+        const double al = (double)pl.dirichlet[J.M * n + sd] - 1.0;
+        double ap;
+        if (pl.dim == 2) {
+            int t = -J.e[1] * K[0] + J.e[0] * K[1];
+            t %= n;
+            if (t < 0) t += n;
+            ap = pl.dirichlet[J.M * n + t];
+        } else {
+            ap = pl.aperp[(size_t)jb * npts + idx];
+        }
+        acc += W * al * ap;
+    }
+    lam[idx] = (float)(acc * inv);
+}
+
+// grad_w[p] = sum over cells of the job partial of the job holding p (0 if none);
+// fixed summation order over cells, in FP64.
+__global__ void k_gw_reduce(DevPlan pl, int batch, const int32_t* __restrict__ dir_job,
+                            const float* __restrict__ part, float* __restrict__ gw)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pl.P) return;
+    const int jb = dir_job[p];
+    double acc = 0.0;
+    if (jb >= 0)
+        for (int c = 0; c < batch; ++c) acc += (double)part[(size_t)c * pl.njobs + jb];
+    gw[p] = (float)acc;
+}
+
+// ------------------------------------------------------------------ dispatch
+int device_cu_count()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+int num_variants(int, int) { return 2; }
+
+namespace {
+
+template <int N>
+constexpr int t3d()
+{
+    return N == 32 ? 512 : (N == 24 ? 576 : (N == 16 ? 256 : 64));
+}
+
+template <int N>
+size_t lds3d(int ntilde) { return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)(ntilde + 1) * N + 64); }
+
+}  // namespace
+
+#define QDVM_SWITCH_3D(N_, BODY)                          \
+    switch (N_) {                                          \
+        case 8: { constexpr int N = 8; BODY; } break;      \
+        case 16: { constexpr int N = 16; BODY; } break;    \
+        case 24: { constexpr int N = 24; BODY; } break;    \
+        case 32: { constexpr int N = 32; BODY; } break;    \
+        default: return hipErrorInvalidValue;              \
+    }
+
+hipError_t launch_prep(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st)
+{
+    const int threads = 256;
+    const int n = std::max(pl.npts, pl.njobs);
+    hipLaunchKernelGGL(k_prep, dim3((n + threads - 1) / threads), dim3(threads), 0, st, pl, w, s.lam, s.jobw);
+    return hipGetLastError();
+}
+
+LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant)
+{
+    LaunchInfo li;
+    hipError_t e = hipSuccess;
+    if (pl.dim == 2) {
+        e = eval2d_info(pl, batch, variant, li);
+    } else {
+        auto body = [&]() -> hipError_t {
+            QDVM_SWITCH_3D(pl.n, {
+                constexpr int T = t3d<N>();
+                li.block = T;
+                li.lds = lds3d<N>(pl.ntilde);
+                e = variant ? occupancy_grid(k_eval3d<N, T, 1>, T, li.lds, batch, li.grid)
+                            : occupancy_grid(k_eval3d<N, T, 0>, T, li.lds, batch, li.grid);
+                li.slots = li.grid;
+            });
+            return e;
+        };
+        e = body();
+    }
+    if (e != hipSuccess) li.grid = 0;
+    return li;
+}
+
+hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, float dt, DevScratch s,
+                       const LaunchInfo& li, int variant, hipStream_t st)
+{
+    if (pl.dim == 2) return launch_eval2d(pl, batch, f, q, dt, s, li, variant, st);
+    QDVM_SWITCH_3D(pl.n, {
+        constexpr int T = t3d<N>();
+        if (variant)
+            hipLaunchKernelGGL((k_eval3d<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, q, dt, s);
+        else
+            hipLaunchKernelGGL((k_eval3d<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, q, dt, s);
+    });
+    return hipGetLastError();
+}
+
+LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant)
+{
+    LaunchInfo li;
+    hipError_t e = hipSuccess;
+    if (pl.dim == 2) {
+        e = vjp2d_info(pl, batch, variant, li);
+    } else {
+        auto body = [&]() -> hipError_t {
+            QDVM_SWITCH_3D(pl.n, {
+                constexpr int T = t3d<N>();
+                li.block = T;
+                li.lds = lds3d<N>(pl.ntilde);
+                e = variant ? occupancy_grid(k_vjp3d<N, T, 1>, T, li.lds, batch, li.grid)
+                            : occupancy_grid(k_vjp3d<N, T, 0>, T, li.lds, batch, li.grid);
+                li.slots = li.grid;
+            });
+            return e;
+        };
+        e = body();
+    }
+    if (e != hipSuccess) li.grid = 0;
+    return li;
+}
+
+hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
+                      float* grad_w, const float* w, DevScratch s, const LaunchInfo& li, int variant,
+                      hipStream_t st)
+{
+    (void)w;
+    hipError_t e = hipSuccess;
+    if (pl.dim == 2) {
+        e = launch_vjp2d(pl, batch, f, c, grad_f, s, li, variant, st);
+    } else {
+        auto body = [&]() -> hipError_t {
+            QDVM_SWITCH_3D(pl.n, {
+                constexpr int T = t3d<N>();
+                if (variant)
+                    hipLaunchKernelGGL((k_vjp3d<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, c,
+                                       grad_f, s);
+                else
+                    hipLaunchKernelGGL((k_vjp3d<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, c,
+                                       grad_f, s);
+            });
+            return hipGetLastError();
+        };
+        e = body();
+    }
+    if (e != hipSuccess) return e;
+    if (grad_w) {
+        hipLaunchKernelGGL(k_gw_reduce, dim3((pl.P + 63) / 64), dim3(64), 0, st, pl, batch, pl.dir_job,
+                           s.gw_part, grad_w);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace qdvm

@@ -1,0 +1,109 @@
+// Device helpers shared by the 2D and 3D collision kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fft_reg.h"
+#include "qdvm_internal.h"
+
+namespace qdvm {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Keep the scheduler from hoisting a whole pencil of loads ahead of their use
+// (which multiplies live registers): fence every 8 elements of a load loop.
+#define QDVM_CHUNK_FENCE(k)                                            \
+    do {                                                               \
+        if (((k) & 7) == 7) __builtin_amdgcn_sched_barrier(0);         \
+    } while (0)
+
+// ------------------------------------------------------------ buffer access
+// Per-element global accesses go through buffer instructions: the base and
+// extent live in a wave-uniform descriptor (SGPRs), the lane's pencil offset
+// in one VGPR and the element stride in the uniform soffset, so a pencil of n
+// elements costs one address register instead of n.  Accesses outside
+// [0, bytes) return 0 / are dropped by the hardware.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ float2 bload2(rsrc_t r, int voff, int soff)
+{
+    // copy the elements to scalars first: bit-casting an ext-vector element
+    // expression directly has been seen to read element 0 for both
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    const unsigned int lo = v[0], hi = v[1];
+    return make_float2(__builtin_bit_cast(float, lo), __builtin_bit_cast(float, hi));
+}
+__device__ __forceinline__ void bstore(float x, rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore2(float2 x, rsrc_t r, int voff, int soff)
+{
+    const float fx = x.x, fy = x.y;
+    u32x2 v;
+    v[0] = __builtin_bit_cast(unsigned int, fx);
+    v[1] = __builtin_bit_cast(unsigned int, fy);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+}
+
+template <int N>
+__device__ __forceinline__ int modc(int x)
+{
+    x %= N;
+    return x < 0 ? x + N : x;
+}
+
+// One pencil transform, fenced so that the scheduler does not interleave
+// neighbouring pencils or phases (which multiplies the live temporaries).
+template <int N, int RV, int SIGN>
+__device__ __forceinline__ void fftp(float2 (&x)[N])
+{
+    __builtin_amdgcn_sched_barrier(0);
+    Radix<N, RV>::template fft<SIGN>(x);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Sum over the n lanes of an aligned lane group.
+template <int N>
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int o = N / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+
+// Grid of a persistent launch: the occupancy-limited number of resident
+// workgroups on the device, capped by the number of work items.
+template <class K>
+inline hipError_t occupancy_grid(K kernel, int block, size_t lds, int items, int& grid)
+{
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int cus = device_cu_count();
+    if (cus < 1) cus = 1;
+    grid = std::min(items, per_cu * cus);
+    if (grid < 1) grid = 1;
+    return hipSuccess;
+}
+
+}  // namespace qdvm

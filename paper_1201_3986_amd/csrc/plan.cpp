@@ -1,0 +1,256 @@
+// Host-side plan construction for the fast DVM collision operator:
+// direction set, line lengths, weights, transform jobs and the FP64-built
+// spectral multiplier tables (rounded once to FP32 for the device).
+//
+// References are to Mouhot, Pareschi, Rey, "Convolutive decomposition and fast
+// summation methods for discrete-velocity approximations of the Boltzmann
+// equation".
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+#include <set>
+#include <tuple>
+
+#include "qdvm_internal.h"
+
+namespace qdvm {
+
+bool supported_size(int dim, int n)
+{
+    if (dim == 2) return n == 8 || n == 16 || n == 32 || n == 64;
+    if (dim == 3) return n == 8 || n == 16 || n == 24 || n == 32;
+    return false;
+}
+
+namespace {
+
+int igcd(int a, int b)
+{
+    a = std::abs(a);
+    b = std::abs(b);
+    while (b) {
+        int t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+using Line = std::vector<int32_t>;
+
+// Canonical order of lines: (|e|_inf, |e|_2^2, components ascending).
+bool line_less(const Line& a, const Line& b)
+{
+    auto key = [](const Line& e) {
+        int inf = 0, n2 = 0;
+        for (int x : e) {
+            inf = std::max(inf, std::abs(x));
+            n2 += x * x;
+        }
+        return std::make_tuple(inf, n2);
+    };
+    auto ka = key(a), kb = key(b);
+    if (ka != kb) return ka < kb;
+    return a < b;
+}
+
+// Lines through 0 of [-order, order]^dim (the set A^{dim-1} of Sec. 3.2), one
+// primitive vector per line with first nonzero component positive.  Built shell
+// by shell in |e|_inf so that the first P lines of a larger order coincide.
+std::vector<Line> lines_of_order(int dim, int order)
+{
+    std::vector<Line> out;
+    for (int shell = 1; shell <= order; ++shell) {
+        std::vector<Line> sh;
+        int side = 2 * shell + 1;
+        int total = 1;
+        for (int a = 0; a < dim; ++a) total *= side;
+        for (int idx = 0; idx < total; ++idx) {
+            Line e(dim);
+            int r = idx, inf = 0, g = 0;
+            for (int a = dim - 1; a >= 0; --a) {
+                e[a] = r % side - shell;
+                r /= side;
+            }
+            for (int x : e) {
+                inf = std::max(inf, std::abs(x));
+                g = igcd(g, x);
+            }
+            if (inf != shell || g != 1) continue;
+            int first = 0;
+            for (int x : e)
+                if (x) {
+                    first = x;
+                    break;
+                }
+            if (first < 0) continue;
+            sh.push_back(e);
+        }
+        std::sort(sh.begin(), sh.end(), line_less);
+        out.insert(out.end(), sh.begin(), sh.end());
+    }
+    return out;
+}
+
+}  // namespace
+
+std::string build_host_plan(int dim, int n, double half_width, int ntilde, int farey_order,
+                            int num_dirs, const int32_t* dirs, const double* weights, HostPlan& hp)
+{
+    char msg[256];
+    if (dim != 2 && dim != 3) return "invalid: dim must be 2 or 3";
+    if (n < 2) return "invalid: n must be at least 2";
+    if (!supported_size(dim, n)) {
+        std::snprintf(msg, sizeof msg, "unsupported: n = %d for dim %d (2D: 8,16,32,64; 3D: 8,16,24,32)", n, dim);
+        return msg;
+    }
+    if (!(half_width > 0.0) || !std::isfinite(half_width)) return "invalid: half_width must be positive and finite";
+    // Default truncation Nt = floor(n / (3 + sqrt 2)) (Sec. 4, next to Table 1).
+    if (ntilde == 0) ntilde = (int)std::floor(n / (3.0 + std::sqrt(2.0)));
+    if (ntilde < 1 || 2 * ntilde + 1 > n) {
+        std::snprintf(msg, sizeof msg, "invalid: ntilde = %d needs 1 <= ntilde and 2*ntilde+1 <= n = %d", ntilde, n);
+        return msg;
+    }
+    std::vector<Line> L;
+    if (dirs) {
+        if (num_dirs < 1 || num_dirs > 65536) return "invalid: num_dirs must be in [1, 65536] with explicit dirs";
+        std::set<Line> seen;
+        for (int p = 0; p < num_dirs; ++p) {
+            Line e(dirs + (size_t)p * dim, dirs + (size_t)(p + 1) * dim);
+            int g = 0, first = 0;
+            for (int x : e) {
+                g = igcd(g, x);
+                if (!first && x) first = x;
+                if (std::abs(x) > 1 << 20) return "invalid: direction component too large";
+            }
+            if (g != 1) {
+                std::snprintf(msg, sizeof msg, "invalid: direction %d is zero or not primitive", p);
+                return msg;
+            }
+            if (first < 0) {
+                std::snprintf(msg, sizeof msg, "invalid: direction %d must have its first nonzero component positive", p);
+                return msg;
+            }
+            if (!seen.insert(e).second) {
+                std::snprintf(msg, sizeof msg, "invalid: direction %d duplicates an earlier line", p);
+                return msg;
+            }
+            L.push_back(e);
+        }
+    } else if (num_dirs > 0) {
+        if (num_dirs > 65536) return "invalid: num_dirs too large";
+        int order = 1;
+        for (;;) {
+            L = lines_of_order(dim, order);
+            if ((int)L.size() >= num_dirs) break;
+            ++order;
+        }
+        L.resize(num_dirs);
+    } else if (farey_order >= 1) {
+        if (farey_order > 64) return "invalid: farey_order too large (max 64)";
+        L = lines_of_order(dim, farey_order);
+    } else {
+        return "invalid: give dirs, num_dirs > 0 or farey_order >= 1";
+    }
+
+    hp.dim = dim;
+    hp.n = n;
+    hp.ntilde = ntilde;
+    hp.half_width = half_width;
+    hp.h = 2.0 * half_width / n;
+    hp.P = (int)L.size();
+    hp.dirs.clear();
+    hp.M.clear();
+    hp.weights.assign(hp.P, 0.0);
+    for (int p = 0; p < hp.P; ++p) {
+        int inf = 0;
+        double n2 = 0;
+        for (int x : L[p]) {
+            hp.dirs.push_back(x);
+            inf = std::max(inf, std::abs(x));
+            n2 += double(x) * x;
+        }
+        hp.M.push_back(ntilde / inf);
+        // a(k) = h^(2d-1) |k| / gcd(k) (Sec. 3.2, after eq. (3.3)): constant on a line
+        hp.weights[p] = weights ? weights[p] : std::pow(hp.h, 2 * dim - 1) * std::sqrt(n2);
+        if (weights && !std::isfinite(weights[p])) return "invalid: weights must be finite";
+    }
+
+    // Jobs: one inverse transform per direction with M >= 1; in 2D a direction
+    // and its perpendicular share one.
+    hp.jobs.clear();
+    std::vector<int> used(hp.P, 0);
+    for (int p = 0; p < hp.P; ++p) {
+        if (hp.M[p] < 1 || used[p]) continue;
+        JobDesc j{};
+        for (int a = 0; a < dim; ++a) j.e[a] = L[p][a];
+        j.M = hp.M[p];
+        j.p = p;
+        j.pp = -1;
+        used[p] = 1;
+        if (dim == 2) {
+            Line perp = {-L[p][1], L[p][0]};
+            if (perp[0] < 0 || (perp[0] == 0 && perp[1] < 0)) perp = {L[p][1], -L[p][0]};
+            for (int r = p + 1; r < hp.P; ++r)
+                if (!used[r] && L[r] == perp) {
+                    j.pp = r;
+                    used[r] = 1;
+                    break;
+                }
+        }
+        hp.jobs.push_back(j);
+    }
+    hp.dir_job.assign(hp.P, -1);
+    for (size_t jb = 0; jb < hp.jobs.size(); ++jb) {
+        hp.dir_job[hp.jobs[jb].p] = (int32_t)jb;
+        if (hp.jobs[jb].pp >= 0) hp.dir_job[hp.jobs[jb].pp] = (int32_t)jb;
+    }
+
+    // Dirichlet table D_M(s) = sum_{|m|<=M} cos(2 pi m s / n), M = 0..Nt, built
+    // in FP64 with the phase m*s reduced mod n in integers.
+    std::vector<double> ct(n);
+    for (int r = 0; r < n; ++r) ct[r] = std::cos(2.0 * M_PI * r / n);
+    hp.dirichlet.assign((size_t)(ntilde + 1) * n, 0.f);
+    for (int M = 0; M <= ntilde; ++M)
+        for (int s = 0; s < n; ++s) {
+            double acc = 1.0;
+            for (int m = 1; m <= M; ++m) acc += 2.0 * ct[(m * s) % n];
+            hp.dirichlet[(size_t)M * n + s] = (float)acc;
+        }
+
+    // 3D plane multipliers alpha'_p(K) = sum_{l.e_p = 0, |l|_inf <= Nt} cos(2 pi K.l / n)
+    // (Sec. 3.2, after eq. (3.6)), stored in the spectral pencil layout
+    // idx = Kz*n^2 + Kx*n + Ky.
+    hp.aperp.clear();
+    if (dim == 3) {
+        const int npts = n * n * n;
+        hp.aperp.assign((size_t)hp.jobs.size() * npts, 0.f);
+        const int side = 2 * ntilde + 1;
+        for (size_t jb = 0; jb < hp.jobs.size(); ++jb) {
+            const JobDesc& J = hp.jobs[jb];
+            std::vector<std::array<int, 3>> pl;
+            for (int a = -ntilde; a <= ntilde; ++a)
+                for (int b = -ntilde; b <= ntilde; ++b)
+                    for (int c = -ntilde; c <= ntilde; ++c)
+                        if (a * J.e[0] + b * J.e[1] + c * J.e[2] == 0) pl.push_back({a, b, c});
+            (void)side;
+            // the multiplier depends on K only through K mod n; sum over the plane set
+            for (int kz = 0; kz < n; ++kz)
+                for (int kx = 0; kx < n; ++kx)
+                    for (int ky = 0; ky < n; ++ky) {
+                        double acc = 0.0;
+                        for (const auto& l : pl) {
+                            int r = (kx * l[0] + ky * l[1] + kz * l[2]) % n;
+                            if (r < 0) r += n;
+                            acc += ct[r];
+                        }
+                        hp.aperp[jb * npts + (size_t)kz * n * n + kx * n + ky] = (float)acc;
+                    }
+        }
+    }
+    return std::string();
+}
+
+}  // namespace qdvm

@@ -1,0 +1,112 @@
+// Internal types shared by the host plan builder and the HIP kernels of the
+// qdvm library.  Nothing here is part of the public C interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace qdvm {
+
+// One inverse transform of the direction loop ("job").  In 2D a line e and its
+// perpendicular e' give the same unit-weight term (Remark 3.5), so a job may
+// carry two directions, whose weights are added.
+struct JobDesc {
+    int32_t e[3];   // primitive representative (third component 0 in 2D)
+    int32_t M;      // floor(Nt / |e|_inf) >= 1: the line sum runs over 0 < |m| <= M
+    int32_t p;      // direction index in the plan
+    int32_t pp;     // paired perpendicular direction, or -1
+};
+
+// Device view of an immutable plan, passed to kernels by value.
+struct DevPlan {
+    int32_t dim, n, ntilde, P, njobs;
+    int32_t npts;                // n^dim
+    const JobDesc* jobs;         // [njobs]
+    const float* dirichlet;      // [(ntilde+1) * n]: D_M(s) = sum_{|m|<=M} cos(2 pi m s / n)
+    const float* aperp;          // 3D: [njobs][npts] plane multipliers, spectral layout; 2D: null
+    const float* w_default;      // [P] default weights
+    const int32_t* dir_job;      // [P] job holding each direction, -1 if M_p = 0
+};
+
+// Per-call scratch carved out of a plan's workspace.
+struct DevScratch {
+    float* lam;      // [npts]  loss multiplier Lambda / npts, spectral layout
+    float* jobw;     // [njobs] combined job weight / npts^2
+    float2* spec;    // [slots * npts] spectrum of f per resident cell slot
+    float2* spec2;   // [slots * npts] second spectral buffer (adjoint)
+    float2* acc;     // [slots * npts] spectral accumulator (adjoint)
+    float* gw_part;  // [batch * njobs] per-cell job partials of grad_w (adjoint)
+    int32_t* counter;  // work-queue counter (batched)
+};
+
+struct HostPlan {
+    int32_t dim = 0, n = 0, ntilde = 0, P = 0;
+    double half_width = 0, h = 0;
+    std::vector<int32_t> dirs;       // P * dim
+    std::vector<double> weights;     // P
+    std::vector<int32_t> M;          // P
+    std::vector<JobDesc> jobs;
+    std::vector<float> dirichlet;    // (ntilde+1) * n
+    std::vector<float> aperp;        // njobs * npts (3D)
+    // device copies
+    JobDesc* d_jobs = nullptr;
+    float* d_dirichlet = nullptr;
+    float* d_aperp = nullptr;
+    float* d_w = nullptr;
+    int32_t* d_dir_job = nullptr;
+    std::vector<int32_t> dir_job;    // P
+    int device = 0;
+    // workspace (grown on demand)
+    void* d_ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t last_stream = nullptr;
+    int npts() const { int t = 1; for (int a = 0; a < dim; ++a) t *= n; return t; }
+    DevPlan dev() const
+    {
+        DevPlan d;
+        d.dim = dim; d.n = n; d.ntilde = ntilde; d.P = P; d.njobs = (int32_t)jobs.size();
+        d.npts = npts();
+        d.jobs = d_jobs; d.dirichlet = d_dirichlet; d.aperp = d_aperp; d.w_default = d_w;
+        d.dir_job = d_dir_job;
+        return d;
+    }
+};
+
+// Host plan construction (no device work).  Returns an empty string on success
+// or a message describing the invalid argument.
+std::string build_host_plan(int dim, int n, double half_width, int ntilde, int farey_order,
+                            int num_dirs, const int32_t* dirs, const double* weights, HostPlan& hp);
+
+bool supported_size(int dim, int n);
+
+// ------------------------------------------------------------- launch API
+// Kernel-side launchers (kernels.hip).  All return hipSuccess or an error.
+struct LaunchInfo {
+    int grid = 0, block = 0;
+    size_t lds = 0;
+    int slots = 0;   // resident cell slots that need spectral scratch
+};
+
+hipError_t launch_prep(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st);
+LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant);
+hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, float dt,
+                       DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
+LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant);
+hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
+                      float* grad_w, const float* w, DevScratch s, const LaunchInfo& li, int variant,
+                      hipStream_t st);
+
+// 2D launchers (kernels_2d.hip), called by the dispatch in kernels_3d.hip.
+hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li);
+hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q, float dt, DevScratch s,
+                         const LaunchInfo& li, int variant, hipStream_t st);
+hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li);
+hipError_t launch_vjp2d(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
+                        DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
+
+int num_variants(int dim, int n);
+int device_cu_count();
+
+}  // namespace qdvm

@@ -1,0 +1,250 @@
+"""Python binding of libqdvm (ctypes): argument marshalling only.
+
+Every step of the collision operator runs in the HIP library; this module
+checks tensor shapes, passes device pointers and the current HIP stream, and
+maps status codes to exceptions.  PyTorch provides device memory and streams.
+If the built library is missing, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libqdvm.so")
+
+QDVM_OK, QDVM_EINVAL, QDVM_EUNSUPPORTED, QDVM_ENOMEM, QDVM_EDEVICE = 0, -1, -2, -3, -4
+
+_lock = threading.Lock()
+_lib = None
+
+
+class QdvmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("qdvm status %d: %s" % (status, message))
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("half_width", ctypes.c_double),
+                ("ntilde", ctypes.c_int32), ("farey_order", ctypes.c_int32), ("num_dirs", ctypes.c_int32),
+                ("dirs", ctypes.POINTER(ctypes.c_int32)), ("weights", ctypes.POINTER(ctypes.c_double))]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("ntilde", ctypes.c_int32),
+                ("num_dirs", ctypes.c_int32), ("num_jobs", ctypes.c_int32), ("h", ctypes.c_double)]
+
+
+def load():
+    """Load libqdvm.so from the package's build folder (raises if absent)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libqdvm.so is not built (%s); run python -m paper_1201_3986_amd.build" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, i32p, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), \
+            ctypes.POINTER(ctypes.c_double)
+        sigs = {
+            "qdvm_plan": [ctypes.POINTER(Desc), ctypes.POINTER(vp)],
+            "qdvm_plan_destroy": [vp],
+            "qdvm_plan_info": [vp, ctypes.POINTER(PlanInfo)],
+            "qdvm_plan_dirs": [vp, i32p, dp, i32p],
+            "qdvm_describe": [ctypes.POINTER(Desc), i32p, i32p, dp, i32p, i32],
+            "qdvm_eval": [vp, i32, vp, vp, vp, ctypes.c_float, vp],
+            "qdvm_vjp": [vp, i32, vp, vp, vp, vp, vp, vp],
+            "qdvm_set_variant": [vp, i32, i32],
+            "qdvm_get_variant": [vp, i32, i32p],
+            "qdvm_autotune": [vp, i32, vp],
+        }
+        for name, args in sigs.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.qdvm_status_string.argtypes = [ctypes.c_int]
+        lib.qdvm_status_string.restype = ctypes.c_char_p
+        lib.qdvm_last_error.restype = ctypes.c_char_p
+        lib.qdvm_abi_version.restype = ctypes.c_int32
+        _lib = lib
+        return lib
+
+
+def _check(status: int):
+    if status != QDVM_OK:
+        lib = load()
+        raise QdvmError(status, lib.qdvm_last_error().decode() or lib.qdvm_status_string(status).decode())
+
+
+def _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights):
+    keep = []
+    d = Desc(dim, n, float(half_width), ntilde, farey_order, num_dirs, None, None)
+    if dirs is not None:
+        a = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1, dim))
+        keep.append(a)
+        d.dirs = a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.num_dirs = a.shape[0]
+    if weights is not None:
+        wv = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        keep.append(wv)
+        d.weights = wv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d, keep
+
+
+def describe(dim, n, half_width=8.0, ntilde=0, farey_order=0, num_dirs=0, dirs=None, weights=None):
+    """Host-only: (dirs, weights, line lengths) a descriptor selects."""
+    lib = load()
+    d, keep = _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights)
+    P = ctypes.c_int32(0)
+    _check(lib.qdvm_describe(ctypes.byref(d), ctypes.byref(P), None, None, None, 0))
+    dirs_out = np.zeros((P.value, dim), dtype=np.int32)
+    w_out = np.zeros(P.value, dtype=np.float64)
+    m_out = np.zeros(P.value, dtype=np.int32)
+    _check(lib.qdvm_describe(ctypes.byref(d), ctypes.byref(P),
+                             dirs_out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             w_out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             m_out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), P.value))
+    return dirs_out, w_out, m_out
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Plan:
+    """An immutable plan (directions, weights, multiplier tables) on the current device."""
+
+    def __init__(self, dim, n, half_width=8.0, ntilde=0, farey_order=0, num_dirs=0, dirs=None, weights=None):
+        lib = load()
+        d, keep = _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights)
+        h = ctypes.c_void_p()
+        _check(lib.qdvm_plan(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        info = PlanInfo()
+        _check(lib.qdvm_plan_info(h, ctypes.byref(info)))
+        self.dim, self.n, self.ntilde = info.dim, info.n, info.ntilde
+        self.num_dirs, self.num_jobs, self.h = info.num_dirs, info.num_jobs, info.h
+        self.npts = self.n ** self.dim
+        self.dirs = np.zeros((self.num_dirs, dim), dtype=np.int32)
+        self.weights = np.zeros(self.num_dirs, dtype=np.float64)
+        self.line_len = np.zeros(self.num_dirs, dtype=np.int32)
+        _check(lib.qdvm_plan_dirs(h, self.dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  self.weights.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  self.line_len.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().qdvm_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _cells(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+            raise TypeError("%s must be a float32 CUDA tensor" % name)
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if t.numel() % self.npts:
+            raise ValueError("%s has %d elements, not a multiple of n^d = %d" % (name, t.numel(), self.npts))
+        return t.numel() // self.npts
+
+    def _weights(self, w):
+        import torch
+        if w is None:
+            return None
+        if not w.is_cuda or w.dtype != torch.float32 or w.numel() != self.num_dirs or not w.is_contiguous():
+            raise ValueError("w must be a contiguous float32 CUDA tensor of %d weights" % self.num_dirs)
+        return w
+
+    def eval(self, f, out=None, w=None, dt=0.0, stream=None):
+        """Q(f, f) (dt == 0) or f + dt Q(f, f) for every cell of f; out may be f."""
+        import torch
+        batch = self._cells(f, "f")
+        if out is None:
+            out = torch.empty_like(f)
+        elif self._cells(out, "out") != batch:
+            raise ValueError("out and f differ in size")
+        w = self._weights(w)
+        _check(load().qdvm_eval(self._h, batch, _ptr(f), _ptr(out), _ptr(w), float(dt), _stream_ptr(stream)))
+        return out
+
+    def vjp(self, f, cot, w=None, want_grad_w=True, stream=None):
+        """(grad_f, grad_w) of <cot, Q(f; w)>, grad_w summed over the cells."""
+        import torch
+        batch = self._cells(f, "f")
+        if self._cells(cot, "cot") != batch:
+            raise ValueError("cot and f differ in size")
+        w = self._weights(w)
+        gf = torch.empty_like(f)
+        gw = torch.empty(self.num_dirs, dtype=torch.float32, device=f.device) if want_grad_w else None
+        _check(load().qdvm_vjp(self._h, batch, _ptr(f), _ptr(cot), _ptr(w), _ptr(gf), _ptr(gw),
+                               _stream_ptr(stream)))
+        return gf, gw
+
+    def set_variant(self, op: int, variant: int):
+        _check(load().qdvm_set_variant(self._h, op, variant))
+
+    def get_variant(self, op: int) -> int:
+        v = ctypes.c_int32(0)
+        _check(load().qdvm_get_variant(self._h, op, ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, batch: int, stream=None):
+        _check(load().qdvm_autotune(self._h, batch, _stream_ptr(stream)))
+
+
+def _make_function():
+    import torch
+
+    class QdvmFunction(torch.autograd.Function):
+        """Q(f; w) with the hand-written adjoint as backward.
+
+        forward(f, w, plan): f float32 CUDA (batch * n^d), w float32 CUDA (P) or None.
+        """
+
+        @staticmethod
+        def forward(ctx, f, w, plan):
+            ctx.plan = plan
+            ctx.save_for_backward(f, w if w is not None else torch.empty(0, device=f.device))
+            ctx.has_w = w is not None
+            return plan.eval(f.contiguous(), w=w)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            f, w = ctx.saved_tensors
+            w = w if ctx.has_w else None
+            need_w = ctx.needs_input_grad[1]
+            gf, gw = ctx.plan.vjp(f, grad_out.contiguous(), w=w, want_grad_w=need_w)
+            return gf, (gw if need_w else None), None
+
+    return QdvmFunction
+
+
+_fn = None
+
+
+def collide(f, plan: Plan, w=None):
+    """Differentiable Q(f; w) through QdvmFunction."""
+    global _fn
+    if _fn is None:
+        _fn = _make_function()
+    return _fn.apply(f, w, plan)
