@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the fast DVM collision operator on one MI355X.
+
+Headline step: one qdvm_eval over a batch of B cells of the 2D workload
+(n = 64 points per axis on [-8, 8)^2, Nt = 14, the first 16 lattice lines,
+two Maxwellians times (1 + 0.05 xi) per cell).  `value` is cells evaluated
+per second (whole job, inputs resident in HBM).  Prints ONE JSON line with
+the roofline of the collision kernel (algorithmic FLOPs / measured duration
+against the FP32 vector peak), the FP64 oracle timed on the host cores, the
+relative error of sampled cells against that oracle, and secondary results:
+the other direction counts, 3D n = 32, the batched heterogeneous Euler step
+and the adjoint.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Q(f,f) evals/sec, 2D N=64 & 3D N=32 at 1e-5 rel err; % HBM roofline; VJP/eval ratio"
+FP32_VECTOR_PEAK_TFLOPS = 157.3      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1201_3986_amd/csrc/kernels_2d.hip", "paper_1201_3986_amd/csrc/kernels_common.h",
+                  "paper_1201_3986_amd/csrc/fft_reg.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(dim, n, jobs):
+    """Per cell: (P_eff + 1) complex transforms of n^d points at 5 N log2 N, the
+    per-direction multiply and product (9 flops per point) and the loss (8)."""
+    npts = n ** dim
+    return (jobs + 1) * 5.0 * npts * math.log2(npts) + 9.0 * jobs * npts + 8.0 * npts
+
+
+def vjp_algorithmic_flops(dim, n, jobs):
+    npts = n ** dim
+    return (2 * jobs + 3) * 5.0 * npts * math.log2(npts) + 20.0 * jobs * npts
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
+    when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    s = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    if not m or not s or s.group(1) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def time_calls(fn, steps, warmup):
+    """Average ms per call, HIP events on the current stream (where the library launches)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def sampled_error(plan, f_np, q_np, idx):
+    import oracle
+    w = np.float32(plan.weights).astype(np.float64)
+    errs = []
+    for c in idx:
+        ref = oracle.collide(plan.dim, plan.n, plan.ntilde, plan.dirs, w, f_np[c].astype(np.float64))
+        errs.append(float(np.max(np.abs(q_np[c].reshape(-1) - ref.reshape(-1))) / np.max(np.abs(ref))))
+    return max(errs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=16384, help="2D n=64 cells per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB elementwise copy (x*1 -> y) to scale HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(cells shard across GPUs without communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1201_3986_amd import qdvm, workloads
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    qdvm.load()
+    results = {}
+
+    # ---------------------------------------------------------------- headline
+    B = args.batch
+    distinct = 256
+    base = workloads.two_maxwellians_batch(202, distinct, 64, noise=0.05)
+    f_np = np.ascontiguousarray(np.tile(base, (B // distinct + 1, 1, 1))[:B])
+    f = torch.from_numpy(f_np).cuda()
+    q = torch.empty_like(f)
+    plan = qdvm.Plan(2, 64, 8.0, num_dirs=16)
+    log("headline: 2D n=64 P=16 jobs=%d batch=%d" % (plan.num_jobs, B))
+    ms = time_calls(lambda: plan.eval(f, out=q), args.steps, args.warmup)
+    value = B / (ms * 1e-3)
+    flops = algorithmic_flops(2, 64, plan.num_jobs) * B
+    achieved = flops / (ms * 1e-3) / 1e12
+    q_np = q.cpu().numpy()
+    err = sampled_error(plan, f_np, q_np, [0, 1, 2, 3, B - 1])
+    log("headline: %.3f ms/step, %.3e cells/s, %.1f TFLOP/s, sampled rel err %.2e" % (ms, value, achieved, err))
+    traffic = recorded_traffic("eval2d_n64_p16_traffic.md")
+    roofline = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+        "traffic": (traffic * 1.0) if traffic is not None else None,
+        "kernel": "k_eval2d<64> (+ k_prep)",
+        "algorithmic_flops_per_cell": algorithmic_flops(2, 64, plan.num_jobs),
+        "hbm_gbs_algorithmic": round(8.0 * 4096 * B / (ms * 1e-3) / 1e9, 1),
+        "hbm_frac_algorithmic": round(8.0 * 4096 * B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+    if args.copy_calibration:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x (read 256 MiB, write 256 MiB) elementwise kernels")
+        del x, y
+
+    # ---------------------------------------------------------------- secondary
+    if not args.no_secondary:
+        for P in (8, 32):
+            pl = qdvm.Plan(2, 64, 8.0, num_dirs=P)
+            t = time_calls(lambda: pl.eval(f, out=q), max(5, args.steps // 4), 2)
+            e = sampled_error(pl, f_np, q.cpu().numpy(), [0, 5])
+            results["2d_n64_P%d" % P] = {"cells_per_s": B / (t * 1e-3), "ms": t, "rel_err": e,
+                                         "tflops": algorithmic_flops(2, 64, pl.num_jobs) * B / (t * 1e-3) / 1e12}
+            pl.close()
+        results["2d_n64_P16"] = {"cells_per_s": value, "ms": ms, "rel_err": err, "tflops": achieved}
+        del f, q
+        torch.cuda.empty_cache()
+
+        C3 = 2048
+        base3 = workloads.three_gaussians_batch(303, 64, 32)
+        f3_np = np.ascontiguousarray(np.tile(base3, (C3 // 64, 1, 1, 1)))
+        f3 = torch.from_numpy(f3_np).cuda()
+        q3 = torch.empty_like(f3)
+        ev3 = {}
+        for P in (8, 16):
+            pl = qdvm.Plan(3, 32, 8.0, num_dirs=P)
+            t = time_calls(lambda: pl.eval(f3, out=q3), max(5, args.steps // 5), 2)
+            e = sampled_error(pl, f3_np, q3.cpu().numpy(), [1])
+            ev3[P] = t
+            results["3d_n32_P%d" % P] = {"cells_per_s": C3 / (t * 1e-3), "ms": t, "rel_err": e,
+                                         "tflops": algorithmic_flops(3, 32, pl.num_jobs) * C3 / (t * 1e-3) / 1e12}
+            log("3D n=32 P=%d: %.3f ms for %d cells, rel err %.2e" % (P, t, C3, e))
+            if P == 16:
+                # adjoint on the differentiation workload shape (64 cells, P = 16)
+                c5 = workloads.c5()
+                fv = torch.from_numpy(c5["f"]).cuda()
+                cv = torch.from_numpy(c5["cot"]).cuda()
+                tv = time_calls(lambda: pl.vjp(fv, cv), max(5, args.steps // 5), 2)
+                te = time_calls(lambda: pl.eval(fv), max(5, args.steps // 5), 2)
+                results["vjp_3d_n32_P16_64cells"] = {
+                    "ms": tv, "eval_ms_same_batch": te, "vjp_over_eval": tv / te,
+                    "cells_per_s": 64 / (tv * 1e-3),
+                    "tflops": vjp_algorithmic_flops(3, 32, pl.num_jobs) * 64 / (tv * 1e-3) / 1e12}
+                log("VJP 3D n=32 P=16 64 cells: %.3f ms (eval %.3f ms, ratio %.2f)" % (tv, te, tv / te))
+            pl.close()
+        del f3, q3
+        torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        threads = oracle.num_threads()
+        w = np.float32(plan.weights).astype(np.float64)
+        cells = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 12.0 and cells < B:
+            oracle.collide(2, 64, plan.ntilde, plan.dirs, w, f_np[cells % distinct].astype(np.float64))
+            cells += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": cells / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": "%d cells of the headline workload (2D n=64, P=16), FP64 direct pair sum, "
+                         "%.1f s wall, OpenMP threads=%d" % (cells, dt, threads)}
+        log("cpu oracle: %.2f cells/s on %d threads" % (cells / dt, threads))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D DVM n=64 on [-8,8)^2, Nt=14, first 16 lattice lines (8 perpendicular "
+                               "pairs), two Maxwellians x (1 + 0.05 U[-1,1]) per cell, %d cells per step" % B,
+                   "dim": 2, "n": 64, "half_width": 8.0, "ntilde": plan.ntilde, "num_dirs": 16,
+                   "cells_per_step": B, "parallelism": "single GPU"},
+        "parity": {"rel_linf_sampled": err, "tolerance": 1e-5},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "results": results,
+    }
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,3 +127,27 @@ def random_positive(seed: int, d: int, n: int, batch: int = 1) -> np.ndarray:
     """Generic positive test field (i.i.d. U[0.1, 1]) for edge-case tests."""
     rng = np.random.default_rng(seed)
     return rng.uniform(0.1, 1.0, size=(batch,) + (n,) * d).astype(np.float32)
+
+
+def two_maxwellians_batch(seed: int, cells: int, n: int, R: float = 8.0, noise: float = 0.0) -> np.ndarray:
+    """`cells` independent draws of the c1/c2 family, shape (cells, n, n), float32.
+    Per cell: T1, c1 (2), T2, c2 (2), then the noise field if noise > 0."""
+    rng = np.random.default_rng(seed)
+    vx, vy = velocity_axes(2, n, R)
+    out = np.empty((cells, n, n), dtype=np.float32)
+    for c in range(cells):
+        f = np.zeros((n, n))
+        for _ in range(2):
+            T = rng.uniform(0.5, 1.5)
+            u = rng.uniform(-2.0, 2.0, size=2)
+            f += np.exp(-((vx - u[0]) ** 2 + (vy - u[1]) ** 2) / (2 * T)) / (2 * np.pi * T)
+        if noise:
+            f *= 1.0 + noise * rng.uniform(-1.0, 1.0, size=f.shape)
+        out[c] = f
+    return out
+
+
+def three_gaussians_batch(seed: int, cells: int, n: int, R: float = 8.0) -> np.ndarray:
+    """`cells` independent draws of the c3 family, shape (cells, n, n, n), float32."""
+    rng = np.random.default_rng(seed)
+    return np.stack([_three_gaussians(rng, 3, n, R) for _ in range(cells)]).astype(np.float32)
