@@ -53,6 +53,8 @@ typedef enum {
 } qdvm_status;
 
 typedef struct qdvm_plan_s* qdvm_plan_t;   /* opaque, immutable after creation */
+typedef struct qdvm_batch_s* qdvm_batch_t; /* opaque heterogeneous batch (cells of several plans) */
+typedef struct qdvm_graph_s* qdvm_graph_t; /* opaque captured Euler step */
 
 /*
  * Plan descriptor: the parameters of Sec. 3.3 (n, the truncation Nt through
@@ -132,6 +134,45 @@ qdvm_status qdvm_eval(qdvm_plan_t plan, int32_t batch, const float* f, float* q,
  */
 qdvm_status qdvm_vjp(qdvm_plan_t plan, int32_t batch, const float* f, const float* cot, const float* w,
                      float* grad_f, float* grad_w, hipStream_t stream);
+
+/*
+ * Heterogeneous batch: many spatial cells, each with its own plan (grid size,
+ * direction set, weights), evaluated in one persistent launch per block-size
+ * family present (family A: 2D n = 8, 16, 32 and 3D n = 24; family B: 2D
+ * n = 64 and 3D n = 32), with a device work queue ordered by cost.  Sec. 3.3
+ * notes that the direction set may vary with position; each cell is the
+ * single-cell operator of its plan.
+ *   cell_plan    host array of ncells plans (the same plan may repeat); every
+ *                plan on the current device.  3D n = 8 and 16 are not
+ *                supported here (EUNSUPPORTED).
+ *   cell_offset  host array of ncells element offsets of each cell in f/q;
+ *                cells must not overlap and the largest offset + n^d must stay
+ *                below 2^29 elements (2 GiB).
+ * The batch holds its work list, plan table, queue counter and scratch on
+ * the device; the plans must outlive it.  Calls on one batch must be ordered.
+ */
+qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const int64_t* cell_offset,
+                            qdvm_batch_t* out);
+qdvm_status qdvm_batch_destroy(qdvm_batch_t batch);   /* synchronises the device first; NULL is a no-op */
+/* launches (kernel launches per evaluation), work items, algorithmic FLOPs of one evaluation;
+ * each output may be NULL */
+qdvm_status qdvm_batch_info(qdvm_batch_t batch, int32_t* launches, int32_t* items, double* flops);
+/* q = Q(f) per cell (dt == 0) or q = f + dt Q(f); f and q are device arrays
+ * addressed by the batch's cell offsets; q may equal f (in place). */
+qdvm_status qdvm_batch_eval(qdvm_batch_t batch, const float* f, float* q, float dt, hipStream_t stream);
+/* One-shot form: builds a batch, evaluates, synchronises `stream`, destroys it. */
+qdvm_status qdvm_eval_batched(int32_t ncells, const qdvm_plan_t* cell_plan, const int64_t* cell_offset,
+                              const float* f, float* q, float dt, hipStream_t stream);
+
+/* Capture one in-place forward-Euler step f <- f + dt Q(f) of a batch (queue
+ * reset kernel + persistent launch, no memset nodes) into a HIP graph on a
+ * non-default stream; each launch replays it on `stream`.  The graph reuses
+ * the batch's device state, so the batch must outlive it and replays must be
+ * ordered. */
+qdvm_status qdvm_step_graph_create(qdvm_batch_t batch, float* f, float dt, hipStream_t capture_stream,
+                                   qdvm_graph_t* out);
+qdvm_status qdvm_step_graph_launch(qdvm_graph_t graph, hipStream_t stream);
+qdvm_status qdvm_step_graph_destroy(qdvm_graph_t graph);
 
 /* Kernel variant (FFT radix order) used by eval (op 0) and vjp (op 1):
  * -1 restores automatic choice.  qdvm_autotune times every variant on

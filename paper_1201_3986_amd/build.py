@@ -22,7 +22,8 @@ ARCH = os.environ.get("QDVM_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", CSRC, "-I", INCLUDE, "-Wall", "-Wno-unused-function"]
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("capi.cpp", False), ("plan.cpp", False), ("kernels_2d.hip", True), ("kernels_3d.hip", True)]
+SOURCES = [("capi.cpp", False), ("plan.cpp", False), ("kernels_2d.hip", True), ("kernels_3d.hip", True),
+           ("kernels_batched.hip", True)]
 
 
 def _hipcc():

@@ -2,6 +2,8 @@
 // workspace and launches.  See include/qdvm.h for the contract of each call.
 #include "../../include/qdvm.h"
 
+#include <string>
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +21,33 @@ struct qdvm_plan_s {
     qdvm::HostPlan hp;
     int variant[2] = {-1, -1};
     std::mutex mu;
+};
+
+struct qdvm_batch_s {
+    struct Family {
+        int fam = 0;
+        std::vector<qdvm::BatchItem> items;
+        std::vector<int64_t> cell_off;
+        std::vector<qdvm::DevPlan> plans;
+        qdvm::BatchItem* d_items = nullptr;
+        int64_t* d_cell_off = nullptr;
+        qdvm::DevPlan* d_plans = nullptr;
+        int32_t* d_counter = nullptr;
+        float2* d_spec = nullptr;
+        qdvm::LaunchInfo li;
+        qdvm::BatchDev dev{};
+    };
+    std::vector<Family> fams;
+    int device = 0;
+    int32_t ncells = 0;
+    uint32_t fbytes = 0;
+    double flops = 0.0;   // algorithmic FLOPs of one evaluation of all cells
+    std::mutex mu;
+};
+
+struct qdvm_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -61,12 +90,16 @@ void free_device(qdvm::HostPlan& hp)
     hipFree(hp.d_aperp);
     hipFree(hp.d_w);
     hipFree(hp.d_dir_job);
+    hipFree(hp.d_lam0);
+    hipFree(hp.d_jobw0);
     hipFree(hp.d_ws);
     hp.d_jobs = nullptr;
     hp.d_dirichlet = nullptr;
     hp.d_aperp = nullptr;
     hp.d_w = nullptr;
     hp.d_dir_job = nullptr;
+    hp.d_lam0 = nullptr;
+    hp.d_jobw0 = nullptr;
     hp.d_ws = nullptr;
     hp.ws_bytes = 0;
 }
@@ -154,8 +187,14 @@ qdvm_status do_eval(qdvm_plan_s* p, int batch, const float* f, float* q, const f
     qdvm_status s = ensure_ws(hp, L.total, st);
     if (s != QDVM_OK) return s;
     qdvm::DevScratch sc = scratch_of(hp, L, false);
-    hipError_t e = qdvm::launch_prep(pl, w ? w : hp.d_w, sc, st);
-    if (e != hipSuccess) return from_hip(e, "launching the multiplier preparation");
+    hipError_t e = hipSuccess;
+    if (w) {
+        e = qdvm::launch_prep(pl, w, sc, st);
+        if (e != hipSuccess) return from_hip(e, "launching the multiplier preparation");
+    } else {
+        sc.lam = hp.d_lam0;
+        sc.jobw = hp.d_jobw0;
+    }
     e = qdvm::launch_eval(pl, batch, f, q, dt, sc, li, variant, st);
     if (e != hipSuccess) return from_hip(e, "launching the collision kernel");
     hp.last_stream = st;
@@ -173,12 +212,67 @@ qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, co
     qdvm_status s = ensure_ws(hp, L.total, st);
     if (s != QDVM_OK) return s;
     qdvm::DevScratch sc = scratch_of(hp, L, true);
-    hipError_t e = qdvm::launch_prep(pl, w ? w : hp.d_w, sc, st);
-    if (e != hipSuccess) return from_hip(e, "launching the multiplier preparation");
+    hipError_t e = hipSuccess;
+    if (w) {
+        e = qdvm::launch_prep(pl, w, sc, st);
+        if (e != hipSuccess) return from_hip(e, "launching the multiplier preparation");
+    } else {
+        sc.lam = hp.d_lam0;
+        sc.jobw = hp.d_jobw0;
+    }
     e = qdvm::launch_vjp(pl, batch, f, c, gf, gw, w ? w : hp.d_w, sc, li, variant, st);
     if (e != hipSuccess) return from_hip(e, "launching the adjoint kernel");
     hp.last_stream = st;
     return QDVM_OK;
+}
+
+
+int batch_class(int dim, int n)
+{
+    if (dim == 2) {
+        switch (n) {
+            case 8: return qdvm::BC_2D8;
+            case 16: return qdvm::BC_2D16;
+            case 32: return qdvm::BC_2D32;
+            case 64: return qdvm::BC_2D64;
+        }
+    } else if (dim == 3) {
+        if (n == 24) return qdvm::BC_3D24;
+        if (n == 32) return qdvm::BC_3D32;
+    }
+    return -1;
+}
+
+int class_family(int c) { return (c == qdvm::BC_2D64 || c == qdvm::BC_3D32) ? qdvm::BF_512 : qdvm::BF_576; }
+
+int class_cells_per_item(int c)
+{
+    switch (c) {
+        case qdvm::BC_2D8: return 576 / 8;
+        case qdvm::BC_2D16: return 576 / 16;
+        case qdvm::BC_2D32: return 576 / 32;
+        case qdvm::BC_2D64: return 512 / 64;
+        default: return 1;
+    }
+}
+
+double cell_flops(const qdvm::HostPlan& hp)
+{
+    const double npts = hp.npts();
+    const double jobs = (double)hp.jobs.size();
+    return (jobs + 1) * 5.0 * npts * std::log2(npts) + 9.0 * jobs * npts + 8.0 * npts;
+}
+
+void free_batch(qdvm_batch_s* b)
+{
+    for (auto& F : b->fams) {
+        hipFree(F.d_items);
+        hipFree(F.d_cell_off);
+        hipFree(F.d_plans);
+        hipFree(F.d_counter);
+        hipFree(F.d_spec);
+    }
+    b->fams.clear();
 }
 
 }  // namespace
@@ -214,6 +308,16 @@ qdvm_status qdvm_plan(const qdvm_desc* desc, qdvm_plan_t* out)
     if (e == hipSuccess) e = upload(&hp.d_aperp, hp.aperp);
     if (e == hipSuccess) e = upload(&hp.d_w, wf);
     if (e == hipSuccess) e = upload(&hp.d_dir_job, hp.dir_job);
+    // Lambda and the job weights for the plan's own weights, computed once
+    if (e == hipSuccess) e = hipMalloc(&hp.d_lam0, sizeof(float) * hp.npts());
+    if (e == hipSuccess) e = hipMalloc(&hp.d_jobw0, sizeof(float) * std::max<size_t>(1, hp.jobs.size()));
+    if (e == hipSuccess) {
+        qdvm::DevScratch sc{};
+        sc.lam = hp.d_lam0;
+        sc.jobw = hp.d_jobw0;
+        e = qdvm::launch_prep(hp.dev(), hp.d_w, sc, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    }
     if (e != hipSuccess) {
         free_device(hp);
         delete p;
@@ -377,6 +481,225 @@ qdvm_status qdvm_autotune(qdvm_plan_t p, int32_t batch, hipStream_t st)
     hipFree(g);
     if (s != QDVM_OK) return s;
     return from_hip(e, "autotuning");
+}
+
+qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const int64_t* cell_offset,
+                            qdvm_batch_t* out)
+{
+    g_last_error.clear();
+    if (!out) return fail(QDVM_EINVAL, "null output pointer");
+    if (ncells < 0) return fail(QDVM_EINVAL, "negative ncells");
+    if (ncells > 0 && (!cell_plan || !cell_offset)) return fail(QDVM_EINVAL, "null cell_plan or cell_offset");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e, "hipGetDevice");
+    int64_t max_end = 0;
+    double flops = 0.0;
+    for (int32_t c = 0; c < ncells; ++c) {
+        const qdvm_plan_s* p = cell_plan[c];
+        if (!p) return fail(QDVM_EINVAL, "null plan for cell " + std::to_string(c));
+        if (p->hp.device != dev) return fail(QDVM_EINVAL, "a plan belongs to another device than the current one");
+        if (batch_class(p->hp.dim, p->hp.n) < 0)
+            return fail(QDVM_EUNSUPPORTED, "batched launch supports 2D n in {8,16,32,64} and 3D n in {24,32}");
+        if (cell_offset[c] < 0) return fail(QDVM_EINVAL, "negative cell offset");
+        max_end = std::max<int64_t>(max_end, cell_offset[c] + p->hp.npts());
+        flops += cell_flops(p->hp);
+    }
+    if (max_end * 4 >= (int64_t(1) << 31)) return fail(QDVM_EINVAL, "f extent must stay below 2 GiB per batch");
+    qdvm_batch_s* b = new (std::nothrow) qdvm_batch_s();
+    if (!b) return fail(QDVM_ENOMEM, "host allocation failed");
+    b->device = dev;
+    b->ncells = ncells;
+    b->fbytes = (uint32_t)(max_end * 4);
+    b->flops = flops;
+    for (int fam = 0; fam < 2; ++fam) {
+        // groups of cells with the same (class, plan), in order of first appearance
+        std::vector<std::pair<std::pair<int, const qdvm_plan_s*>, std::vector<int32_t>>> groups;
+        for (int32_t c = 0; c < ncells; ++c) {
+            const qdvm_plan_s* p = cell_plan[c];
+            const int cls = batch_class(p->hp.dim, p->hp.n);
+            if (class_family(cls) != fam) continue;
+            auto key = std::make_pair(cls, p);
+            size_t gi = 0;
+            while (gi < groups.size() && groups[gi].first != key) ++gi;
+            if (gi == groups.size()) groups.push_back({key, {}});
+            groups[gi].second.push_back(c);
+        }
+        if (groups.empty()) continue;
+        qdvm_batch_s::Family F;
+        F.fam = fam;
+        std::vector<const qdvm_plan_s*> plan_of_slot;
+        struct Tmp {
+            qdvm::BatchItem it;
+            std::vector<int32_t> cells;
+            double cost;
+        };
+        std::vector<Tmp> tmp;
+        size_t dtab_floats = 1;
+        for (auto& g : groups) {
+            const int cls = g.first.first;
+            const qdvm_plan_s* p = g.first.second;
+            int slot = -1;
+            for (size_t k = 0; k < plan_of_slot.size(); ++k)
+                if (plan_of_slot[k] == p) slot = (int)k;
+            if (slot < 0) {
+                slot = (int)plan_of_slot.size();
+                plan_of_slot.push_back(p);
+                F.plans.push_back(p->hp.dev());
+                dtab_floats = std::max<size_t>(dtab_floats, (size_t)(p->hp.ntilde + 1) * p->hp.n);
+            }
+            const int cpi = class_cells_per_item(cls);
+            for (size_t k = 0; k < g.second.size(); k += cpi) {
+                Tmp t;
+                t.it.cls = cls;
+                t.it.plan = slot;
+                t.it.count = (int32_t)std::min<size_t>(cpi, g.second.size() - k);
+                t.cells.assign(g.second.begin() + k, g.second.begin() + k + t.it.count);
+                t.cost = cell_flops(p->hp) * t.it.count;
+                tmp.push_back(t);
+            }
+        }
+        // most expensive items first, so the tail of the queue is made of small ones
+        std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& c) { return a.cost > c.cost; });
+        for (auto& t : tmp) {
+            t.it.first = (int32_t)F.cell_off.size();
+            for (int32_t c : t.cells) F.cell_off.push_back(cell_offset[c]);
+            F.items.push_back(t.it);
+        }
+        e = qdvm::batched_launch_info(fam, (int)F.items.size(), F.li, dtab_floats);
+        if (e != hipSuccess || F.li.grid <= 0) {
+            free_batch(b);
+            delete b;
+            return from_hip(e == hipSuccess ? hipErrorInvalidValue : e, "configuring the batched kernel");
+        }
+        const size_t slot_elems = qdvm::batched_slot_elems(fam);
+        e = hipMalloc(&F.d_items, sizeof(qdvm::BatchItem) * F.items.size());
+        if (e == hipSuccess) e = hipMemcpy(F.d_items, F.items.data(), sizeof(qdvm::BatchItem) * F.items.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&F.d_cell_off, sizeof(int64_t) * F.cell_off.size());
+        if (e == hipSuccess) e = hipMemcpy(F.d_cell_off, F.cell_off.data(), sizeof(int64_t) * F.cell_off.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&F.d_plans, sizeof(qdvm::DevPlan) * F.plans.size());
+        if (e == hipSuccess) e = hipMemcpy(F.d_plans, F.plans.data(), sizeof(qdvm::DevPlan) * F.plans.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&F.d_counter, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&F.d_spec, sizeof(float2) * slot_elems * F.li.grid);
+        if (e != hipSuccess) {
+            b->fams.push_back(F);
+            free_batch(b);
+            delete b;
+            return from_hip(e, "allocating the batch tables");
+        }
+        F.dev.items = F.d_items;
+        F.dev.nitems = (int32_t)F.items.size();
+        F.dev.plans = F.d_plans;
+        F.dev.cell_off = F.d_cell_off;
+        F.dev.counter = F.d_counter;
+        F.dev.spec = F.d_spec;
+        F.dev.slot_elems = (int64_t)slot_elems;
+        F.dev.fbytes = b->fbytes;
+        F.dev.dtab_floats = (int32_t)dtab_floats;
+        b->fams.push_back(F);
+    }
+    *out = b;
+    return QDVM_OK;
+}
+
+qdvm_status qdvm_batch_destroy(qdvm_batch_t b)
+{
+    if (!b) return QDVM_OK;
+    qdvm_status st = QDVM_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) st = from_hip(e, "synchronising before destroying the batch");
+    free_batch(b);
+    delete b;
+    return st;
+}
+
+qdvm_status qdvm_batch_info(qdvm_batch_t b, int32_t* launches, int32_t* items, double* flops)
+{
+    if (!b) return fail(QDVM_EINVAL, "null batch");
+    int32_t n = 0;
+    for (auto& F : b->fams) n += (int32_t)F.items.size();
+    if (launches) *launches = (int32_t)b->fams.size();
+    if (items) *items = n;
+    if (flops) *flops = b->flops;
+    return QDVM_OK;
+}
+
+qdvm_status qdvm_batch_eval(qdvm_batch_t b, const float* f, float* q, float dt, hipStream_t st)
+{
+    if (!b) return fail(QDVM_EINVAL, "null batch");
+    if (b->ncells == 0) return QDVM_OK;
+    if (!f || !q) return fail(QDVM_EINVAL, "null f or q");
+    if (!std::isfinite(dt)) return fail(QDVM_EINVAL, "dt must be finite");
+    std::lock_guard<std::mutex> lock(b->mu);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e, "hipGetDevice");
+    if (dev != b->device) return fail(QDVM_EINVAL, "batch belongs to another device than the current one");
+    for (auto& F : b->fams) {
+        e = qdvm::launch_batched(F.fam, F.dev, F.li, f, q, dt, st);
+        if (e != hipSuccess) return from_hip(e, "launching the batched kernel");
+    }
+    return QDVM_OK;
+}
+
+qdvm_status qdvm_eval_batched(int32_t ncells, const qdvm_plan_t* cell_plan, const int64_t* cell_offset,
+                              const float* f, float* q, float dt, hipStream_t st)
+{
+    qdvm_batch_t b = nullptr;
+    qdvm_status s = qdvm_batch_plan(ncells, cell_plan, cell_offset, &b);
+    if (s != QDVM_OK) return s;
+    s = qdvm_batch_eval(b, f, q, dt, st);
+    if (s == QDVM_OK) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) s = from_hip(e, "synchronising the batched evaluation");
+    }
+    qdvm_status s2 = qdvm_batch_destroy(b);
+    return s != QDVM_OK ? s : s2;
+}
+
+qdvm_status qdvm_step_graph_create(qdvm_batch_t b, float* f, float dt, hipStream_t st, qdvm_graph_t* out)
+{
+    if (!b || !f || !out) return fail(QDVM_EINVAL, "null batch, f or output");
+    if (!st) return fail(QDVM_EINVAL, "graph capture needs a non-default stream");
+    if (!std::isfinite(dt)) return fail(QDVM_EINVAL, "dt must be finite");
+    std::lock_guard<std::mutex> lock(b->mu);
+    qdvm_graph_s* g = new (std::nothrow) qdvm_graph_s();
+    if (!g) return fail(QDVM_ENOMEM, "host allocation failed");
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete g;
+        return from_hip(e, "beginning stream capture");
+    }
+    hipError_t le = hipSuccess;
+    for (auto& F : b->fams) {
+        le = qdvm::launch_batched(F.fam, F.dev, F.li, f, f, dt, st);
+        if (le != hipSuccess) break;
+    }
+    e = hipStreamEndCapture(st, &g->graph);
+    if (le == hipSuccess && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        return from_hip(le != hipSuccess ? le : e, "capturing the Euler step");
+    }
+    *out = g;
+    return QDVM_OK;
+}
+
+qdvm_status qdvm_step_graph_launch(qdvm_graph_t g, hipStream_t st)
+{
+    if (!g) return fail(QDVM_EINVAL, "null graph");
+    return from_hip(hipGraphLaunch(g->exec, st), "launching the step graph");
+}
+
+qdvm_status qdvm_step_graph_destroy(qdvm_graph_t g)
+{
+    if (!g) return QDVM_OK;
+    hipError_t e = hipSuccess;
+    if (g->exec) e = hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+    return from_hip(e, "destroying the step graph");
 }
 
 const char* qdvm_status_string(qdvm_status s)

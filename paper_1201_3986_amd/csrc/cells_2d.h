@@ -1,0 +1,243 @@
+// Device code of one 2D cell of the fast DVM collision operator (included by
+// the uniform-batch and the heterogeneous-batch kernels).
+//
+// Mouhot, Pareschi, Rey, Sec. 3.2: under the decoupling (3.3) the kernel modes
+// split over lattice directions (3.6), and each direction of the operator
+// (3.7) is a pair of convolutions of f -- along the line e_p Z (multiplier
+// alpha_p) and along e_p^perp (multiplier alpha'_p) -- multiplied pointwise,
+// minus f times the convolution with alpha_p alpha'_p (the loss).  Both
+// multipliers are real and even, so one complex inverse transform of
+// (alpha_p + i alpha'_p) fhat gives the line sum g_p as its real part and the
+// perpendicular sum h_p as its imaginary part; the losses of all directions
+// are one transform of Lambda fhat, Lambda = sum_p w_p alpha_p alpha'_p:
+//
+//     Q = sum_p w_p g_p h_p - f * IFFT(Lambda fhat).
+//
+// In 2D, alpha_p(K) = D_M(e.K) - 1 and alpha'_p(K) = D_M(e_perp.K) with the
+// Dirichlet kernel D_M(s) = sum_{|m|<=M} cos(2 pi m s / n), so both come from
+// one small LDS table.  A direction and its perpendicular share a transform
+// (their unit-weight terms are equal, Remark 3.5), with weights added.
+//
+// Layout: a cell is n lanes of one wave, lane j owning one pencil in VGPRs.
+//   real space: lane j holds column j,  z[i0] = f(i0, j)    (coalesced I/O)
+//   spectrum:   lane j holds row K0 = j, z[K1] = fhat(j, K1); scratch and
+//               tables are stored [K1][K0] so that lane loads are coalesced.
+// Moving between axes is a transpose through LDS inside the wave.
+// Transforms are unnormalised; 1/n^2 factors sit in Lambda and in the job
+// weights W_j / n^4 prepared by k_prep.
+#pragma once
+#include "kernels_common.h"
+
+namespace qdvm {
+
+// Lane j of an n-lane group holds row j of an n x n matrix; afterwards it holds
+// row j of the transpose.  Row stride n+1 keeps both phases bank-conflict free.
+template <int N>
+__device__ __forceinline__ void group_transpose(float2 (&z)[N], float* xb, int j)
+{
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < N; ++c) xb[j * (N + 1) + c] = z[c].x;
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < N; ++c) z[c].x = xb[c * (N + 1) + j];
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < N; ++c) xb[j * (N + 1) + c] = z[c].y;
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < N; ++c) z[c].y = xb[c * (N + 1) + j];
+}
+
+template <int N, int RV>
+__device__ __forceinline__ void fwd2d(float2 (&z)[N], float* xb, int j)
+{
+    fftp<N, RV, -1>(z);
+    group_transpose<N>(z, xb, j);
+    fftp<N, RV, -1>(z);
+}
+
+template <int N, int RV>
+__device__ __forceinline__ void inv2d(float2 (&z)[N], float* xb, int j)
+{
+    fftp<N, RV, 1>(z);
+    group_transpose<N>(z, xb, j);
+    fftp<N, RV, 1>(z);
+}
+
+// Indices into the Dirichlet table for a job at (K0 = j, K1 = k): s = e.K,
+// t = e_perp.K (mod n), with e_perp = (-e1, e0); both advance linearly in K1.
+struct Mult2D {
+    int s, t, ds, dt;
+    const float* D;
+};
+
+template <int N>
+__device__ __forceinline__ Mult2D mult2d_init(const JobDesc& J, const float* dtab, int j)
+{
+    Mult2D m;
+    m.s = modc<N>(J.e[0] * j);
+    m.t = modc<N>(-J.e[1] * j);
+    m.ds = modc<N>(J.e[1]);
+    m.dt = modc<N>(J.e[0]);
+    m.D = dtab + J.M * N;
+    return m;
+}
+
+template <int N>
+__device__ __forceinline__ void mult2d_step(Mult2D& m)
+{
+    m.s += m.ds;
+    m.s -= (m.s >= N) ? N : 0;
+    m.t += m.dt;
+    m.t -= (m.t >= N) ? N : 0;
+}
+
+// Buffers of one workgroup item (cpb consecutive cells).
+struct Item2D {
+    rsrc_t f, q, fh;     // cell data and the block's spectral scratch
+    int vcell;           // byte offset of this lane's pencil in cell arrays (float)
+    int vspec;           // byte offset of this lane's pencil in spectral arrays (float2)
+};
+
+template <int N, int RV>
+__device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it, rsrc_t rlam,
+                                            const float* __restrict__ jobw, float dt, bool valid, float* xb,
+                                            const float* dtab, int j)
+{
+    constexpr int RS = N * 4, RS2 = N * 8;   // element strides in bytes
+    float2 z[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
+    fwd2d<N, RV>(z, xb, j);
+#pragma unroll
+    for (int k = 0; k < N; ++k) bstore2(z[k], it.fh, it.vspec, k * RS2);
+
+    // loss: l = Re IFFT(Lambda fhat); acc = -f l
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float l = bload(rlam, j * 4, k * RS);
+        z[k].x *= l;
+        z[k].y *= l;
+    }
+    inv2d<N, RV>(z, xb, j);
+    float acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = -bload(it.f, it.vcell, i * RS) * z[i].x;
+
+    // direction loop: g + i h = IFFT((alpha + i alpha') fhat), acc += W g h
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const float cw = jobw[jb];
+        Mult2D m = mult2d_init<N>(J, dtab, j);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const float2 F = bload2(it.fh, it.vspec, k * RS2);
+            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
+            z[k] = make_float2(al * F.x - ap * F.y, al * F.y + ap * F.x);
+            mult2d_step<N>(m);
+            QDVM_CHUNK_FENCE(k);
+        }
+        inv2d<N, RV>(z, xb, j);
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
+    }
+
+    if (!valid) return;
+    if (dt == 0.f) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            bstore(__builtin_fmaf(dt, acc[i], bload(it.f, it.vcell, i * RS)), it.q, it.vcell, i * RS);
+    }
+}
+
+// Adjoint of one 2D cell; the algebra is written out above cell3d_vjp.
+template <int N, int RV>
+__device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, rsrc_t rc, rsrc_t rch,
+                                           rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
+                                           float* __restrict__ gwp, bool valid, float inv_n2, float inv_n,
+                                           float* xb, const float* dtab, int j)
+{
+    constexpr int RS = N * 4, RS2 = N * 8;
+    float2 z[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
+    fwd2d<N, RV>(z, xb, j);
+#pragma unroll
+    for (int k = 0; k < N; ++k) bstore2(z[k], it.fh, it.vspec, k * RS2);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        z[i] = make_float2(bload(rc, it.vcell, i * RS) * bload(it.f, it.vcell, i * RS), 0.f);
+    fwd2d<N, RV>(z, xb, j);
+    // IFFT(Lambda (fhat + i F(cf))) = l + i C_Lambda(cf)
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        bstore2(z[k], rch, it.vspec, k * RS2);
+        const float2 F = bload2(it.fh, it.vspec, k * RS2);
+        const float l = bload(rlam, j * 4, k * RS);
+        z[k] = make_float2(l * (F.x - z[k].y), l * (F.y + z[k].x));
+        QDVM_CHUNK_FENCE(k);
+    }
+    inv2d<N, RV>(z, xb, j);
+    float acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = -bload(rc, it.vcell, i * RS) * z[i].x - z[i].y;
+
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const float cw = jobw[jb];
+        float spart = 0.f;
+        Mult2D m = mult2d_init<N>(J, dtab, j);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const float2 F = bload2(it.fh, it.vspec, k * RS2);
+            const float2 C = bload2(rch, it.vspec, k * RS2);
+            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
+            z[k] = make_float2(al * F.x - ap * F.y, al * F.y + ap * F.x);
+            spart = __builtin_fmaf(al * ap, C.x * F.x + C.y * F.y, spart);
+            mult2d_step<N>(m);
+            QDVM_CHUNK_FENCE(k);
+        }
+        inv2d<N, RV>(z, xb, j);   // z = u + i v = n^2 (g + i h)
+        float rpart = 0.f;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const float c = bload(rc, it.vcell, i * RS);
+            rpart = __builtin_fmaf(c * z[i].x, z[i].y, rpart);
+            z[i] = make_float2(c * z[i].y, c * z[i].x);   // c v + i c u
+            QDVM_CHUNK_FENCE(i);
+        }
+        const float tot = group_sum<N>(rpart * inv_n2 - spart * inv_n);
+        if (j == 0 && valid) gwp[jb] = tot;
+        fwd2d<N, RV>(z, xb, j);
+        m = mult2d_init<N>(J, dtab, j);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
+            // S += W (alpha - i alpha') Y
+            float2 t = make_float2(cw * (al * z[k].x + ap * z[k].y), cw * (al * z[k].y - ap * z[k].x));
+            if (jb > 0) {
+                const float2 sv = bload2(rsh, it.vspec, k * RS2);
+                t.x += sv.x;
+                t.y += sv.y;
+            }
+            bstore2(t, rsh, it.vspec, k * RS2);
+            mult2d_step<N>(m);
+            QDVM_CHUNK_FENCE(k);
+        }
+    }
+    if (pl.njobs > 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) z[k] = bload2(rsh, it.vspec, k * RS2);
+        inv2d<N, RV>(z, xb, j);
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] += z[i].x;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
+}
+
+}  // namespace qdvm

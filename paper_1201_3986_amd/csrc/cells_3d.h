@@ -1,0 +1,285 @@
+// Device code of one 3D cell of the fast DVM collision operator (included by
+// the uniform-batch and the heterogeneous-batch kernels).  The algebra is the
+// one described at the top of kernels_2d.hip; in 3D the plane multiplier
+// alpha'_p(K) = sum_{l.e_p = 0, |l|_inf <= Nt} cos(2 pi K.l / n) comes from a
+// per-direction table built in FP64 on the host.
+#pragma once
+#include "kernels_common.h"
+
+namespace qdvm {
+
+// ------------------------------------------------------------------ 3D cell
+// Pencil phases (element index e runs along the pencil):
+//   X: pencil pi = y*n + z, e = x      (real space; coalesced I/O at x*n^2 + pi)
+//   Y: pencil pi = x*n + z, e = y
+//   Z: pencil pi = x*n + y, e = z      (spectral; scratch/tables at Kz*n^2 + pi)
+// LDS address of (x, y, z): x*SX + y*(n+1) + z, SX = n*(n+1).
+template <int N, int PH>
+__device__ __forceinline__ int addr3(int pi, int e)
+{
+    constexpr int SY = N + 1, SX = N * (N + 1);
+    const int a = pi / N, b = pi % N;
+    if (PH == 0) return e * SX + a * SY + b;
+    if (PH == 1) return a * SX + e * SY + b;
+    return a * SX + b * SY + e;
+}
+
+template <int N, int T, int Q, int PA, int PB>
+__device__ __forceinline__ void block_transpose(float2 (&z)[Q][N], float* xb, int tid)
+{
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < N; ++e) xb[addr3<N, PA>(tid + q * T, e)] = part ? z[q][e].y : z[q][e].x;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const float v = xb[addr3<N, PB>(tid + q * T, e)];
+                if (part) z[q][e].y = v;
+                else z[q][e].x = v;
+            }
+    }
+}
+
+template <int N, int T, int Q, int RV>
+__device__ __forceinline__ void fwd3d(float2 (&z)[Q][N], float* xb, int tid)
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, -1>(z[q]);
+    block_transpose<N, T, Q, 0, 1>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, -1>(z[q]);
+    block_transpose<N, T, Q, 1, 2>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, -1>(z[q]);
+}
+
+template <int N, int T, int Q, int RV>
+__device__ __forceinline__ void inv3d(float2 (&z)[Q][N], float* xb, int tid)
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
+    block_transpose<N, T, Q, 2, 1>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
+    block_transpose<N, T, Q, 1, 0>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
+}
+
+template <int N, int T, int Q>
+__device__ __forceinline__ float block_sum(float v, float* red, int tid)
+{
+    v = group_sum<64>(v);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < (T + 63) / 64; ++w) t += red[w];
+    return t;
+}
+
+// Buffers of one 3D cell: lane pencil pi = tid + q*T, element e at pi + e*n^2.
+struct Cell3D {
+    rsrc_t f, q, fh;
+};
+
+template <int N, int T, int RV>
+__device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl, rsrc_t rlam,
+                                            const float* __restrict__ jobw, float dt, float* xb,
+                                            const float* dtab, int tid)
+{
+    constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
+    float2 z[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
+            const float l = bload(rlam, (tid + q * T) * 4, k * RS);
+            z[q][k].x *= l;
+            z[q][k].y *= l;
+            QDVM_CHUNK_FENCE(k);
+        }
+    inv3d<N, T, Q, RV>(z, xb, tid);
+    float acc[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) acc[q][x] = -bload(cl.f, (tid + q * T) * 4, x * RS) * z[q][x].x;
+
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const float cw = jobw[jb];
+        const float* D = dtab + J.M * N;
+        const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+        const int ds = modc<N>(J.e[2]);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
+                z[q][k] = make_float2(al * F.x - a2 * F.y, al * F.y + a2 * F.x);
+                sidx += ds;
+                sidx -= (sidx >= N) ? N : 0;
+                QDVM_CHUNK_FENCE(k);
+            }
+        }
+        inv3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) acc[q][x] = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, acc[q][x]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+            const int v = (tid + q * T) * 4;
+            bstore(dt == 0.f ? acc[q][x] : __builtin_fmaf(dt, acc[q][x], bload(cl.f, v, x * RS)), cl.q, v, x * RS);
+        }
+}
+
+// Adjoint of one cell.  With c the cotangent and unnormalised transforms F:
+//   l + i C(cf) = IFFT(Lambda (fhat + i F(cf)))            (both real)
+//   per job:  u + i v = IFFT((a + i a') fhat) = n^d (g + i h)
+//             dQ/dw_j part: <c, g h> - <cf, l_j>, the second term by Parseval:
+//             n^{-2d} sum_x c u v - n^{-d} sum_K a a' Re(conj(F(cf)) fhat)
+//             S += W_j / n^{2d} (a - i a') F(c v + i c u)
+//   grad_f = Re IFFT(S) - c l - C(cf)
+// which uses A(c h) + B(c g) = Re IFFT((a - i a') F(c h + i c g)), valid because
+// the multipliers a = alpha_j and a' = alpha'_j are real and even.
+template <int N, int T, int RV>
+__device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, rsrc_t rc, rsrc_t rch,
+                                           rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
+                                           float* __restrict__ gwp, float inv_n2, float inv_n, float* xb,
+                                           float* red, const float* dtab, int tid)
+{
+    constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
+    float2 z[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < N; ++k) bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+            const int v = (tid + q * T) * 4;
+            z[q][x] = make_float2(bload(rc, v, x * RS) * bload(cl.f, v, x * RS), 0.f);
+            QDVM_CHUNK_FENCE(x);
+        }
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const int pi = tid + q * T;
+            bstore2(z[q][k], rch, pi * 8, k * RS2);
+            const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+            const float l = bload(rlam, pi * 4, k * RS);
+            z[q][k] = make_float2(l * (F.x - z[q][k].y), l * (F.y + z[q][k].x));
+            QDVM_CHUNK_FENCE(k);
+        }
+    inv3d<N, T, Q, RV>(z, xb, tid);
+    float acc[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) acc[q][x] = -bload(rc, (tid + q * T) * 4, x * RS) * z[q][x].x - z[q][x].y;
+
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const float cw = jobw[jb];
+        const float* D = dtab + J.M * N;
+        const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+        const int ds = modc<N>(J.e[2]);
+        float spart = 0.f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+                const float2 C = bload2(rch, pi * 8, k * RS2);
+                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
+                z[q][k] = make_float2(al * F.x - a2 * F.y, al * F.y + a2 * F.x);
+                spart = __builtin_fmaf(al * a2, C.x * F.x + C.y * F.y, spart);
+                sidx += ds;
+                sidx -= (sidx >= N) ? N : 0;
+                QDVM_CHUNK_FENCE(k);
+            }
+        }
+        inv3d<N, T, Q, RV>(z, xb, tid);
+        float rpart = 0.f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) {
+                const float c = bload(rc, (tid + q * T) * 4, x * RS);
+                rpart = __builtin_fmaf(c * z[q][x].x, z[q][x].y, rpart);
+                z[q][x] = make_float2(c * z[q][x].y, c * z[q][x].x);
+                QDVM_CHUNK_FENCE(x);
+            }
+        const float tot = block_sum<N, T, Q>(rpart * inv_n2 - spart * inv_n, red, tid);
+        if (tid == 0) gwp[jb] = tot;
+        fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
+                float2 t = make_float2(cw * (al * z[q][k].x + a2 * z[q][k].y),
+                                       cw * (al * z[q][k].y - a2 * z[q][k].x));
+                if (jb > 0) {
+                    const float2 sv = bload2(rsh, pi * 8, k * RS2);
+                    t.x += sv.x;
+                    t.y += sv.y;
+                }
+                bstore2(t, rsh, pi * 8, k * RS2);
+                sidx += ds;
+                sidx -= (sidx >= N) ? N : 0;
+                QDVM_CHUNK_FENCE(k);
+            }
+        }
+    }
+    if (pl.njobs > 0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int k = 0; k < N; ++k) z[q][k] = bload2(rsh, (tid + q * T) * 8, k * RS2);
+        inv3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) acc[q][x] += z[q][x].x;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) bstore(acc[q][x], cl.q, (tid + q * T) * 4, x * RS);
+}
+
+}  // namespace qdvm

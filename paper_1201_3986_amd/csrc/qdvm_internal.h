@@ -28,6 +28,8 @@ struct DevPlan {
     const float* aperp;          // 3D: [njobs][npts] plane multipliers, spectral layout; 2D: null
     const float* w_default;      // [P] default weights
     const int32_t* dir_job;      // [P] job holding each direction, -1 if M_p = 0
+    const float* lam0;           // [npts] Lambda / npts for the default weights
+    const float* jobw0;          // [njobs] job weights / npts^2 for the default weights
 };
 
 // Per-call scratch carved out of a plan's workspace.
@@ -56,6 +58,8 @@ struct HostPlan {
     float* d_aperp = nullptr;
     float* d_w = nullptr;
     int32_t* d_dir_job = nullptr;
+    float* d_lam0 = nullptr;
+    float* d_jobw0 = nullptr;
     std::vector<int32_t> dir_job;    // P
     int device = 0;
     // workspace (grown on demand)
@@ -70,6 +74,8 @@ struct HostPlan {
         d.npts = npts();
         d.jobs = d_jobs; d.dirichlet = d_dirichlet; d.aperp = d_aperp; d.w_default = d_w;
         d.dir_job = d_dir_job;
+        d.lam0 = d_lam0;
+        d.jobw0 = d_jobw0;
         return d;
     }
 };
@@ -105,6 +111,31 @@ hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q,
 hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li);
 hipError_t launch_vjp2d(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
                         DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
+
+// ------------------------------------------------------------- heterogeneous batch
+enum BatchClass : int32_t { BC_2D8 = 0, BC_2D16 = 1, BC_2D32 = 2, BC_2D64 = 3, BC_3D24 = 4, BC_3D32 = 5 };
+enum BatchFamily : int32_t { BF_576 = 0, BF_512 = 1 };
+
+struct BatchItem {
+    int32_t cls, plan, first, count;   // class, plan slot, first entry in cell_off, cells
+};
+
+struct BatchDev {
+    const BatchItem* items;
+    int32_t nitems;
+    const DevPlan* plans;
+    const int64_t* cell_off;   // element offset of each cell, in item order
+    int32_t* counter;
+    float2* spec;              // [grid][slot_elems]
+    int64_t slot_elems;
+    uint32_t fbytes;           // extent of f and q in bytes
+    int32_t dtab_floats;       // LDS floats reserved for the Dirichlet table
+};
+
+hipError_t batched_launch_info(int family, int nitems, LaunchInfo& li, size_t dtab_floats);
+size_t batched_slot_elems(int family);
+hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, const float* f, float* q, float dt,
+                          hipStream_t st);
 
 int num_variants(int dim, int n);
 int device_cu_count();

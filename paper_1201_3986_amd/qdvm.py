@@ -61,6 +61,14 @@ def load():
             "qdvm_set_variant": [vp, i32, i32],
             "qdvm_get_variant": [vp, i32, i32p],
             "qdvm_autotune": [vp, i32, vp],
+            "qdvm_batch_plan": [i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp)],
+            "qdvm_batch_destroy": [vp],
+            "qdvm_batch_info": [vp, i32p, i32p, dp],
+            "qdvm_batch_eval": [vp, vp, vp, ctypes.c_float, vp],
+            "qdvm_eval_batched": [i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), vp, vp, ctypes.c_float, vp],
+            "qdvm_step_graph_create": [vp, vp, ctypes.c_float, vp, ctypes.POINTER(vp)],
+            "qdvm_step_graph_launch": [vp, vp],
+            "qdvm_step_graph_destroy": [vp],
         }
         for name, args in sigs.items():
             fn = getattr(lib, name)
@@ -210,6 +218,98 @@ class Plan:
 
     def autotune(self, batch: int, stream=None):
         _check(load().qdvm_autotune(self._h, batch, _stream_ptr(stream)))
+
+
+def _plan_array(plans):
+    arr = (ctypes.c_void_p * len(plans))()
+    for i, p in enumerate(plans):
+        arr[i] = p.handle.value
+    return arr
+
+
+class BatchPlan:
+    """Heterogeneous batch: cell i uses plans[i] and lives at f[offsets[i] : offsets[i] + n_i^d]."""
+
+    def __init__(self, plans, offsets):
+        lib = load()
+        self._plans = list(plans)            # plans must outlive the batch
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        if len(self._plans) != len(self.offsets):
+            raise ValueError("plans and offsets differ in length")
+        self.extent = int(max((o + p.npts for p, o in zip(self._plans, self.offsets)), default=0))
+        h = ctypes.c_void_p()
+        _check(lib.qdvm_batch_plan(len(self._plans), _plan_array(self._plans),
+                                   self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(h)))
+        self._h = h
+        la, it, fl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib.qdvm_batch_info(h, ctypes.byref(la), ctypes.byref(it), ctypes.byref(fl)))
+        self.launches, self.items, self.flops = la.value, it.value, fl.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check_buf(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous float32 CUDA tensor" % name)
+        if t.numel() < self.extent:
+            raise ValueError("%s has %d elements, the batch addresses %d" % (name, t.numel(), self.extent))
+
+    def eval(self, f, out=None, dt=0.0, stream=None):
+        import torch
+        self._check_buf(f, "f")
+        if out is None:
+            out = torch.empty_like(f)
+        self._check_buf(out, "out")
+        _check(load().qdvm_batch_eval(self._h, _ptr(f), _ptr(out), float(dt), _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().qdvm_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StepGraph:
+    """In-place Euler step f <- f + dt Q(f) of a batch, captured once into a HIP graph."""
+
+    def __init__(self, batch: BatchPlan, f, dt, capture_stream):
+        batch._check_buf(f, "f")
+        self._batch, self._f = batch, f
+        h = ctypes.c_void_p()
+        _check(load().qdvm_step_graph_create(batch.handle, _ptr(f), float(dt),
+                                             ctypes.c_void_p(capture_stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load().qdvm_step_graph_launch(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().qdvm_step_graph_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_batched(plans, offsets, f, out, dt=0.0, stream=None):
+    """One-shot heterogeneous evaluation (synchronises the stream)."""
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    _check(load().qdvm_eval_batched(len(plans), _plan_array(plans),
+                                    offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    _ptr(f), _ptr(out), float(dt), _stream_ptr(stream)))
+    return out
 
 
 def _make_function():

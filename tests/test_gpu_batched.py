@@ -1,0 +1,189 @@
+"""GPU heterogeneous batch (one persistent launch per block-size family) and
+the graph-captured Euler step.
+
+* batched results equal the single-cell path bit for bit (same device code,
+  same multipliers) and the FP64 oracle on sampled cells (<= 1e-5 of max|Q|);
+* mixed grid sizes, plans and ragged work items; in-place Euler updates;
+* the captured step is replayed several times with eager work between the
+  replays, and every replay is checked against the eager result.
+"""
+import numpy as np
+import pytest
+
+from paper_1201_3986_amd import workloads
+from parity_util import oracle_q, rel_linf
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def loss_total(plan, f):
+    """sum_i f_i l_i, l = sum_p w_p (line * plane convolution of f), via numpy FFTs."""
+    n, d = plan.n, plan.dim
+    f = np.asarray(f, np.float64).reshape((n,) * d)
+    F = np.fft.fftn(f)
+    tot = np.zeros_like(f)
+    import itertools
+    box = list(itertools.product(range(-plan.ntilde, plan.ntilde + 1), repeat=d))
+    for e, w, M in zip(plan.dirs, np.float32(plan.weights).astype(np.float64), plan.line_len):
+        if M == 0:
+            continue
+        IK = np.zeros(f.shape)
+        for m in range(-M, M + 1):
+            if m:
+                IK[tuple((m * e) % n)] += 1.0
+        IL = np.zeros(f.shape)
+        for l in box:
+            if int(np.dot(l, e)) == 0:
+                IL[tuple(np.array(l) % n)] += 1.0
+        tot += w * np.fft.ifftn(F * np.fft.fftn(IK) * np.fft.fftn(IL)).real
+    return float(np.sum(f * tot))
+
+
+def _layout(cells):
+    """cells: list of (plan, array) -> flat f, offsets (with gaps between cells)."""
+    offs, pos = [], 0
+    for plan, a in cells:
+        offs.append(pos)
+        pos += plan.npts + 37            # gaps: offsets need not be packed
+    flat = np.full(pos, -7.0, dtype=np.float32)
+    for (plan, a), o in zip(cells, offs):
+        flat[o:o + plan.npts] = a.reshape(-1)
+    return flat, np.array(offs, dtype=np.int64)
+
+
+def test_mixed_batch_equals_single_cell_and_oracle(gpu_lib):
+    import torch
+    p32 = gpu_lib.Plan(2, 32, 8.0, num_dirs=16)
+    p32b = gpu_lib.Plan(2, 32, 8.0, num_dirs=7)
+    p16 = gpu_lib.Plan(2, 16, 8.0, farey_order=4)
+    p24 = gpu_lib.Plan(3, 24, 8.0, num_dirs=16)
+    rng = np.random.default_rng(4)
+    cells = []
+    for i in range(45):           # 2D n=32: 2.5 items of 18 cells, two plans interleaved
+        cells.append((p32 if i % 3 else p32b, workloads.random_positive(500 + i, 2, 32)[0]))
+    for i in range(3):
+        cells.append((p24, workloads.random_positive(600 + i, 3, 24)[0]))
+    for i in range(40):           # 2D n=16: 36 cells per item
+        cells.append((p16, workloads.random_positive(700 + i, 2, 16)[0]))
+    order = rng.permutation(len(cells))
+    cells = [cells[k] for k in order]
+    flat, offs = _layout(cells)
+    b = gpu_lib.BatchPlan([c[0] for c in cells], offs)
+    assert b.launches == 1
+    fd = _dev(flat)
+    qd = b.eval(fd)
+    torch.cuda.synchronize()
+    q = qd.cpu().numpy()
+    for k, ((plan, a), o) in enumerate(zip(cells, offs)):
+        single = plan.eval(_dev(a))
+        torch.cuda.synchronize()
+        assert np.array_equal(q[o:o + plan.npts], single.cpu().numpy().reshape(-1)), k
+    for k in (0, 7, len(cells) - 1):
+        plan, a = cells[k]
+        o = offs[k]
+        err = rel_linf(q[o:o + plan.npts], oracle_q(plan, a))
+        assert err <= TOL, (k, err)
+
+
+def test_two_families_and_in_place_euler(gpu_lib):
+    import torch
+    p64 = gpu_lib.Plan(2, 64, 8.0, num_dirs=16)
+    p32 = gpu_lib.Plan(3, 32, 8.0, num_dirs=8)
+    p8 = gpu_lib.Plan(2, 8, 4.0, ntilde=2, num_dirs=4)
+    cells = [(p64, workloads.random_positive(800 + i, 2, 64)[0]) for i in range(11)]
+    cells += [(p32, workloads.random_positive(900 + i, 3, 32)[0]) for i in range(2)]
+    cells += [(p8, workloads.random_positive(950 + i, 2, 8)[0]) for i in range(5)]
+    flat, offs = _layout(cells)
+    b = gpu_lib.BatchPlan([c[0] for c in cells], offs)
+    assert b.launches == 2
+    dt = 0.01
+    x = _dev(flat)
+    b.eval(x, out=x, dt=dt)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy()
+    for (plan, a), o in zip(cells, offs):
+        ref = plan.eval(_dev(a), dt=dt)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[o:o + plan.npts], ref.cpu().numpy().reshape(-1))
+    # gaps between cells untouched
+    mask = np.ones(len(flat), bool)
+    for (plan, a), o in zip(cells, offs):
+        mask[o:o + plan.npts] = False
+    assert np.all(got[mask] == -7.0)
+
+
+def test_unsupported_and_invalid(gpu_lib):
+    p16 = gpu_lib.Plan(3, 16, 8.0, num_dirs=8)
+    with pytest.raises(gpu_lib.QdvmError) as ei:
+        gpu_lib.BatchPlan([p16], [0])
+    assert ei.value.status == gpu_lib.QDVM_EUNSUPPORTED
+    p = gpu_lib.Plan(2, 32, 8.0, num_dirs=8)
+    with pytest.raises(gpu_lib.QdvmError) as ei:
+        gpu_lib.BatchPlan([p], [-5])
+    assert ei.value.status == gpu_lib.QDVM_EINVAL
+
+
+def test_config4_graph_step(gpu_lib):
+    """The batched inhomogeneous workload: 4096 2D n=32 cells then 512 3D n=24
+    cells, P = 16, one captured forward-Euler step with dt = 0.01."""
+    import torch
+    wl = workloads.c4()
+    c2, c3 = wl["classes"]
+    p2 = gpu_lib.Plan(2, 32, 8.0, num_dirs=16)
+    p3 = gpu_lib.Plan(3, 24, 8.0, num_dirs=16)
+    f2, f3 = c2["f"].reshape(len(c2["f"]), -1), c3["f"].reshape(len(c3["f"]), -1)
+    plans = [p2] * len(f2) + [p3] * len(f3)
+    offs = np.concatenate([np.arange(len(f2)) * 1024, len(f2) * 1024 + np.arange(len(f3)) * 13824]).astype(np.int64)
+    flat = np.concatenate([f2.reshape(-1), f3.reshape(-1)]).astype(np.float32)
+    b = gpu_lib.BatchPlan(plans, offs)
+    assert b.launches == 1
+    dt = wl["dt"]
+    # eager reference trajectory
+    ref = _dev(flat)
+    eager = []
+    for _ in range(3):
+        b.eval(ref, out=ref, dt=dt)
+        torch.cuda.synchronize()
+        eager.append(ref.cpu().numpy())
+    # graph on a side stream, replayed with eager work and synchronisation between replays
+    x = _dev(flat)
+    s = torch.cuda.Stream()
+    g = gpu_lib.StepGraph(b, x, dt, s)
+    for k in range(3):
+        g.launch(stream=s)
+        s.synchronize()
+        scratch = torch.ones(1 << 20, device="cuda") * 3.0       # unrelated eager work
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), eager[k]), k
+        del scratch
+    # physics of one step: mass per cell, positivity, and Q against the oracle
+    q = b.eval(_dev(flat))
+    torch.cuda.synchronize()
+    qn = q.cpu().numpy()
+    step1 = eager[0]
+    # Prop. 3.3: the step keeps f >= 0 when dt * (loss frequency) < 1; in FP32
+    # the tails may dip below zero by at most the rounding of dt * Q
+    print("config4: min after one step %.3e, max f %.3e" % (np.min(step1), np.max(flat)))
+    assert np.min(step1) >= -dt * TOL * np.max(np.abs(qn))
+    # mass residual per cell relative to the total loss it balances (sum_i f_i l_i)
+    worst_mass = 0.0
+    for i in range(len(plans)):
+        o, n = offs[i], plans[i].npts
+        qi = qn[o:o + n].astype(np.float64)
+        worst_mass = max(worst_mass, abs(qi.sum()) / loss_total(plans[i], flat[o:o + n]))
+    print("config4: worst per-cell mass residual (relative to the loss) %.3e" % worst_mass)
+    errs = []
+    for i in list(range(0, len(f2), 512)) + [len(f2), len(f2) + 511]:
+        o, plan = offs[i], plans[i]
+        errs.append(rel_linf(qn[o:o + plan.npts], oracle_q(plan, flat[o:o + plan.npts])))
+    print("config4: sampled cell rel errors (plain FP32): %s" % " ".join("%.2e" % e for e in errs))
+    assert worst_mass <= 1e-6
+    # plain FP32 cannot reach 1e-5 of max|Q| on these near-equilibrium cells
+    # (gain and loss are 50-100x larger than Q); the near-equilibrium mode does.
+    assert max(errs) <= 1e-4
