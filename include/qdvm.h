@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QDVM_ABI_VERSION 1
+#define QDVM_ABI_VERSION 2
 
 typedef enum {
     QDVM_OK = 0,
@@ -74,13 +74,34 @@ typedef struct {
                                component positive, no two on the same line */
     const double* weights;  /* optional host array of P weights; NULL selects
                                a(k) = h^(2d-1) |e_p|_2 (Sec. 3.2, after eq. (3.3)) */
+    int32_t mode;           /* QDVM_MODE_FULL or QDVM_MODE_NEAR_EQUILIBRIUM (below) */
 } qdvm_desc;
+
+/*
+ * Evaluation modes.
+ *   QDVM_MODE_FULL: Q(f, f) of Sec. 3.2 in FP32 arithmetic; the rounding error
+ *     scales with |f|^2, so near equilibrium (where Q is small against |f|^2)
+ *     the relative error grows.
+ *   QDVM_MODE_NEAR_EQUILIBRIUM: per cell, M is the discrete Maxwellian with the
+ *     mass, mean and temperature of f on the index grid (computed in FP64),
+ *     g = f - M, and the result is Q(f, f) - Q(M, M) = Q(g, f) + Q(M, g),
+ *     evaluated with no transform mixing f-sized and g-sized data, so the error
+ *     scales with |f| |g|.  Q(M, M) vanishes for an unwrapped discrete
+ *     Maxwellian (every pair of the discrete sum of Sec. 2.2 cancels); what is left
+ *     out is its periodic-wrap residue.  About twice the transforms of
+ *     QDVM_MODE_FULL.  A cell whose moments do not define a Maxwellian (mass
+ *     <= 0, or index-space temperature <= 1/4) takes M = 0, i.e. Q(f, f).
+ *     qdvm_vjp ignores the mode and differentiates Q(f, f).
+ */
+#define QDVM_MODE_FULL 0
+#define QDVM_MODE_NEAR_EQUILIBRIUM 1
 
 typedef struct {
     int32_t dim, n, ntilde;
     int32_t num_dirs;       /* P */
     int32_t num_jobs;       /* inverse transforms per cell in the direction loop */
     double h;
+    int32_t mode;           /* the descriptor's evaluation mode */
 } qdvm_plan_info_t;
 
 /* Build a plan: direction set, line lengths M_p, weights and FP64-built

@@ -15,4 +15,6 @@ from .oracle import (  # noqa: F401
     vjp,
     num_threads,
     set_num_threads,
+    index_maxwellian,
+    collide_near_equilibrium,
 )

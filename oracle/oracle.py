@@ -167,3 +167,36 @@ def num_threads() -> int:
 
 def set_num_threads(t: int) -> None:
     _load().oracle_set_num_threads(int(t))
+
+
+def index_maxwellian(d: int, n: int, f) -> np.ndarray:
+    """The Maxwellian of the near-equilibrium evaluation, per cell, in FP64.
+
+    On the index grid i in {0..n-1}^d: mass s0 = sum f, mean mu = sum i f / s0,
+    temperature var = (sum |i|^2 f / s0 - |mu|^2) / d, and
+    M(i) = s0 (2 pi var)^(-d/2) exp(-|i - mu|^2 / (2 var)) (the Maxwellian of
+    Sec. 2.1 written in grid units).  A cell with s0 <= 0, var <= 1/4 or
+    non-finite moments gets M = 0.  Returns an array of the shape of f.
+    """
+    flat, batch = _cells(f, d, n)
+    cells = flat.reshape(batch, n ** d)
+    idx = np.stack(np.meshgrid(*([np.arange(n, dtype=np.float64)] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    r2 = np.sum(idx * idx, axis=1)
+    out = np.zeros_like(cells)
+    for c in range(cells.shape[0]):
+        v = cells[c]
+        s0 = v.sum()
+        with np.errstate(all="ignore"):
+            mu = (idx * v[:, None]).sum(axis=0) / s0
+            var = ((r2 * v).sum() / s0 - np.dot(mu, mu)) / d
+        if not (s0 > 0 and np.isfinite(var) and var > 0.25 and np.all(np.isfinite(mu))):
+            continue
+        dist2 = np.sum((idx - mu) ** 2, axis=1)
+        out[c] = s0 * (2.0 * np.pi * var) ** (-d / 2.0) * np.exp(-dist2 / (2.0 * var))
+    return out.reshape(np.shape(f))
+
+
+def collide_near_equilibrium(d, n, ntilde, dirs, w, f) -> np.ndarray:
+    """Q(f, f) - Q(M, M) with M = index_maxwellian(f), both by direct summation."""
+    M = index_maxwellian(d, n, f)
+    return collide(d, n, ntilde, dirs, w, f) - collide(d, n, ntilde, dirs, w, M)

@@ -128,8 +128,11 @@ WsLayout ws_layout(const qdvm::HostPlan& hp, int slots, int batch, bool adjoint)
     L.lam = off; off = align_up(off + sizeof(float) * npts);
     L.jobw = off; off = align_up(off + sizeof(float) * std::max<size_t>(1, hp.jobs.size()));
     L.spec = off; off = align_up(off + sizeof(float2) * npts * slots);
+    if (adjoint || hp.mode) {
+        // adjoint: one slot set; near-equilibrium evaluation: g and a staging set
+        L.spec2 = off; off = align_up(off + sizeof(float2) * npts * slots * (adjoint ? 1 : 2));
+    }
     if (adjoint) {
-        L.spec2 = off; off = align_up(off + sizeof(float2) * npts * slots);
         L.acc = off; off = align_up(off + sizeof(float2) * npts * slots);
         L.gw = off; off = align_up(off + sizeof(float) * std::max<size_t>(1, hp.jobs.size()) * batch);
     }
@@ -166,8 +169,8 @@ qdvm::DevScratch scratch_of(const qdvm::HostPlan& hp, const WsLayout& L, bool ad
     s.lam = (float*)(b + L.lam);
     s.jobw = (float*)(b + L.jobw);
     s.spec = (float2*)(b + L.spec);
+    if (adjoint || hp.mode) s.spec2 = (float2*)(b + L.spec2);
     if (adjoint) {
-        s.spec2 = (float2*)(b + L.spec2);
         s.acc = (float2*)(b + L.acc);
         s.gw_part = (float*)(b + L.gw);
     }
@@ -260,6 +263,8 @@ double cell_flops(const qdvm::HostPlan& hp)
 {
     const double npts = hp.npts();
     const double jobs = (double)hp.jobs.size();
+    if (hp.mode == QDVM_MODE_NEAR_EQUILIBRIUM)   // transforms of f and g, two per job, two losses
+        return (2 * jobs + 4) * 5.0 * npts * std::log2(npts) + 18.0 * jobs * npts + 16.0 * npts;
     return (jobs + 1) * 5.0 * npts * std::log2(npts) + 9.0 * jobs * npts + 8.0 * npts;
 }
 
@@ -296,11 +301,14 @@ qdvm_status qdvm_plan(const qdvm_desc* desc, qdvm_plan_t* out)
         delete p;
         return fail(QDVM_EINVAL, "plan construction failed");
     }
+    if (msg.empty() && desc->mode != QDVM_MODE_FULL && desc->mode != QDVM_MODE_NEAR_EQUILIBRIUM)
+        msg = "invalid: mode must be QDVM_MODE_FULL (0) or QDVM_MODE_NEAR_EQUILIBRIUM (1)";
     if (!msg.empty()) {
         delete p;
         return from_plan_msg(msg);
     }
     qdvm::HostPlan& hp = p->hp;
+    hp.mode = desc->mode;
     hipError_t e = hipGetDevice(&hp.device);
     std::vector<float> wf(hp.weights.begin(), hp.weights.end());
     if (e == hipSuccess) e = upload(&hp.d_jobs, hp.jobs);
@@ -375,6 +383,7 @@ qdvm_status qdvm_plan_info(qdvm_plan_t p, qdvm_plan_info_t* info)
     info->num_dirs = p->hp.P;
     info->num_jobs = (int32_t)p->hp.jobs.size();
     info->h = p->hp.h;
+    info->mode = p->hp.mode;
     return QDVM_OK;
 }
 
@@ -535,7 +544,8 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
             double cost;
         };
         std::vector<Tmp> tmp;
-        size_t dtab_floats = 1;
+        size_t dtab_floats = 2;
+        bool any_split = false;
         for (auto& g : groups) {
             const int cls = g.first.first;
             const qdvm_plan_s* p = g.first.second;
@@ -547,6 +557,7 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
                 plan_of_slot.push_back(p);
                 F.plans.push_back(p->hp.dev());
                 dtab_floats = std::max<size_t>(dtab_floats, (size_t)(p->hp.ntilde + 1) * p->hp.n);
+                any_split = any_split || p->hp.mode == QDVM_MODE_NEAR_EQUILIBRIUM;
             }
             const int cpi = class_cells_per_item(cls);
             for (size_t k = 0; k < g.second.size(); k += cpi) {
@@ -566,13 +577,15 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
             for (int32_t c : t.cells) F.cell_off.push_back(cell_offset[c]);
             F.items.push_back(t.it);
         }
-        e = qdvm::batched_launch_info(fam, (int)F.items.size(), F.li, dtab_floats);
+        dtab_floats = (dtab_floats + 1) & ~size_t(1);
+        e = qdvm::batched_launch_info(fam, (int)F.items.size(), any_split, F.li, dtab_floats);
         if (e != hipSuccess || F.li.grid <= 0) {
             free_batch(b);
             delete b;
             return from_hip(e == hipSuccess ? hipErrorInvalidValue : e, "configuring the batched kernel");
         }
-        const size_t slot_elems = qdvm::batched_slot_elems(fam);
+        const size_t base_slot = qdvm::batched_slot_elems(fam);
+        const size_t slot_elems = any_split ? 3 * base_slot : base_slot;   // f, g and staging spectra
         e = hipMalloc(&F.d_items, sizeof(qdvm::BatchItem) * F.items.size());
         if (e == hipSuccess) e = hipMemcpy(F.d_items, F.items.data(), sizeof(qdvm::BatchItem) * F.items.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMalloc(&F.d_cell_off, sizeof(int64_t) * F.cell_off.size());
@@ -594,6 +607,7 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
         F.dev.counter = F.d_counter;
         F.dev.spec = F.d_spec;
         F.dev.slot_elems = (int64_t)slot_elems;
+        F.dev.gslot = any_split ? (int64_t)base_slot : 0;
         F.dev.fbytes = b->fbytes;
         F.dev.dtab_floats = (int32_t)dtab_floats;
         b->fams.push_back(F);

@@ -154,6 +154,152 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
     }
 }
 
+
+// Sum of a double over the n lanes of an aligned lane group.
+template <int N>
+__device__ __forceinline__ double group_sumd(double v)
+{
+#pragma unroll
+    for (int o = N / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Near-equilibrium evaluation of one 2D cell.  With M the Maxwellian of the
+// cell's moments (FP64) and g = f - M, the bilinear identity
+//     Q(f, f) - Q(M, M) = Q(g, f) + Q(M, g)
+// is evaluated with every transform carrying either f-sized or g-sized data,
+// never both (a small signal packed with a large one in one complex transform
+// inherits rounding of the large one's size):
+//     gain_j = line_j(g) plane_j(f) + (line_j(f) - line_j(g)) plane_j(g)
+//     loss   = g l(f) + M l(g).
+// Q(M, M) vanishes except for aliasing (every bracket of an unwrapped discrete
+// Maxwellian cancels, Sec. 2.2), and is left out: the result is
+// Q(f, f) - Q(M, M).  Errors scale with |f| |g| instead of |f|^2.
+// M is recomputed from its parameters where needed (FP64 exp) instead of being
+// kept in registers.  With STAGE the transform of g of each job is parked in
+// the buffer rtg (same layout as the spectra) while the transform of f is
+// formed, for launches whose register budget cannot hold both.
+template <int N, int RV, bool STAGE>
+__device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2D& it, rsrc_t rgh, rsrc_t rtg,
+                                                  rsrc_t rlam, const float* __restrict__ jobw, float dt, bool valid,
+                                                  float* xb, const float* dtab, int j)
+{
+    constexpr int RS = N * 4, RS2 = N * 8;
+    // moments in index units (column j holds the points (i, j)), FP64
+    double s0 = 0.0, sa = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double v = bload(it.f, it.vcell, i * RS);
+        s0 += v;
+        sa += (double)i * v;
+        s2 += (double)(i * i) * v;
+    }
+    double sb = (double)j * s0;
+    s2 += (double)(j * j) * s0;
+    s0 = group_sumd<N>(s0);
+    sa = group_sumd<N>(sa);
+    sb = group_sumd<N>(sb);
+    s2 = group_sumd<N>(s2);
+    const double m0 = sa / s0, m1 = sb / s0;
+    const double var = 0.5 * (s2 / s0 - m0 * m0 - m1 * m1);
+    // a cell without a usable Gaussian fit keeps M = 0, i.e. the plain evaluation
+    // (its parameters are replaced so that no NaN of 0/0 reaches M)
+    const bool ok = s0 > 0.0 && var > 0.25 && __builtin_isfinite(var) && __builtin_isfinite(m0) &&
+                    __builtin_isfinite(m1);
+    const double mu0 = ok ? m0 : 0.0, mu1 = ok ? m1 : 0.0;
+    const double inv2v = ok ? 0.5 / var : 0.0;
+    const double ej = ok ? s0 / (2.0 * kPi * var) * exp(-(j - mu1) * (j - mu1) * inv2v) : 0.0;
+    // M(i, j) in FP64
+#define QDVM_MAXW(i) (ej * exp(-((i) - mu0) * ((i) - mu0) * inv2v))
+
+    float2 z[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        z[i] = make_float2((float)((double)bload(it.f, it.vcell, i * RS) - QDVM_MAXW(i)), 0.f);
+    fwd2d<N, RV>(z, xb, j);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        bstore2(z[k], rgh, it.vspec, k * RS2);
+        const float l = bload(rlam, j * 4, k * RS);
+        z[k].x *= l;
+        z[k].y *= l;
+        QDVM_CHUNK_FENCE(k);
+    }
+    inv2d<N, RV>(z, xb, j);                      // l(g)
+    float acc[N];                                // holds l(g) until l(f) is formed
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = z[i].x;
+#pragma unroll
+    for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
+    fwd2d<N, RV>(z, xb, j);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        bstore2(z[k], it.fh, it.vspec, k * RS2);
+        const float l = bload(rlam, j * 4, k * RS);
+        z[k].x *= l;
+        z[k].y *= l;
+        QDVM_CHUNK_FENCE(k);
+    }
+    inv2d<N, RV>(z, xb, j);                      // l(f)
+    {
+        // M again (kept opaque so it is not carried over from the first evaluation)
+        const double iv = opaque(inv2v);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const double m = ej * exp(-((i) - mu0) * ((i) - mu0) * iv);
+            const float g = (float)((double)bload(it.f, it.vcell, i * RS) - m);
+            acc[i] = -__builtin_fmaf(g, z[i].x, (float)m * acc[i]);
+        }
+    }
+#undef QDVM_MAXW
+
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const float cw = jobw[jb];
+        float2 tg[N];
+        Mult2D m = mult2d_init<N>(J, dtab, j);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const float2 G = bload2(rgh, it.vspec, k * RS2);
+            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
+            tg[k] = make_float2(al * G.x - ap * G.y, al * G.y + ap * G.x);
+            mult2d_step<N>(m);
+            QDVM_CHUNK_FENCE(k);
+        }
+        inv2d<N, RV>(tg, xb, j);                 // line(g) + i plane(g)
+        if constexpr (STAGE) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) bstore2(tg[i], rtg, it.vspec, i * RS2);
+        }
+        m = mult2d_init<N>(J, dtab, j);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const float2 F = bload2(it.fh, it.vspec, k * RS2);
+            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
+            z[k] = make_float2(al * F.x - ap * F.y, al * F.y + ap * F.x);
+            mult2d_step<N>(m);
+            QDVM_CHUNK_FENCE(k);
+        }
+        inv2d<N, RV>(z, xb, j);                  // line(f) + i plane(f)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const float2 t = STAGE ? bload2(rtg, it.vspec, i * RS2) : tg[i];
+            const float gain = __builtin_fmaf(t.x, z[i].y, (z[i].x - t.x) * t.y);
+            acc[i] = __builtin_fmaf(cw, gain, acc[i]);
+        }
+    }
+
+    if (!valid) return;
+    if (dt == 0.f) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            bstore(__builtin_fmaf(dt, acc[i], bload(it.f, it.vcell, i * RS)), it.q, it.vcell, i * RS);
+    }
+}
+
 // Adjoint of one 2D cell; the algebra is written out above cell3d_vjp.
 template <int N, int RV>
 __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, rsrc_t rc, rsrc_t rch,

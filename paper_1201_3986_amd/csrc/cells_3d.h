@@ -154,6 +154,191 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
         }
 }
 
+
+// Block-wide sum of five doubles (moments); every thread gets the totals.
+template <int T>
+__device__ __forceinline__ void block_sum5d(double (&v)[5], double* red, int tid)
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    __syncthreads();
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) red[(tid >> 6) * 5 + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < (T + 63) / 64; ++w) t += red[w * 5 + k];
+        v[k] = t;
+    }
+}
+
+// Near-equilibrium evaluation of one 3D cell: Q(f, f) - Q(M, M) through
+// Q(g, f) + Q(M, g), g = f - M, M the Maxwellian of the cell's moments (the
+// transform layout, the error argument and STAGE are those of
+// cell2d_eval_split).
+template <int N, int T, int RV, bool STAGE>
+__device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3D& cl, rsrc_t rgh, rsrc_t rtg,
+                                                  rsrc_t rlam, const float* __restrict__ jobw, float dt, float* xb,
+                                                  double* red, const float* dtab, int tid)
+{
+    constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
+    double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum f, sum x f, sum y f, sum z f, sum |x|^2 f
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int pi = tid + q * T, py = pi / N, pz = pi % N;
+        double ps = 0.0;
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+            const double v = bload(cl.f, pi * 4, x * RS);
+            ps += v;
+            mom[1] += (double)x * v;
+            mom[4] += (double)(x * x) * v;
+        }
+        mom[0] += ps;
+        mom[2] += (double)py * ps;
+        mom[3] += (double)pz * ps;
+        mom[4] += (double)(py * py + pz * pz) * ps;
+    }
+    block_sum5d<T>(mom, red, tid);
+    const double s0 = mom[0];
+    const double mx = mom[1] / s0, my = mom[2] / s0, mz = mom[3] / s0;
+    const double var = (mom[4] / s0 - mx * mx - my * my - mz * mz) / 3.0;
+    const bool ok = s0 > 0.0 && var > 0.25 && __builtin_isfinite(var) && __builtin_isfinite(mx) &&
+                    __builtin_isfinite(my) && __builtin_isfinite(mz);
+    const double inv2v = ok ? 0.5 / var : 0.0;
+    const double C = ok ? s0 / ((2.0 * kPi * var) * sqrt(2.0 * kPi * var)) : 0.0;
+    // M(x, y, z) = eyz(y, z) ex(x): the n factors ex(x) sit in LDS after the
+    // reduction slots (block_sum5d uses at most 45 doubles)
+    static_assert(T <= 576, "reduction slots overlap the Maxwellian factors");
+    double* ex = red + 48;
+    if (tid < N) ex[tid] = ok ? exp(-(tid - mx) * (tid - mx) * inv2v) : 0.0;
+    double eyz[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int pi = tid + q * T, py = pi / N, pz = pi % N;
+        eyz[q] = ok ? C * exp(-((py - my) * (py - my) + (pz - mz) * (pz - mz)) * inv2v) : 0.0;
+    }
+    __syncthreads();
+#define QDVM_MAXW3(q, x) (eyz[q] * ex[x])
+
+    float2 z[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x)
+            z[q][x] = make_float2((float)((double)bload(cl.f, (tid + q * T) * 4, x * RS) - QDVM_MAXW3(q, x)), 0.f);
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            bstore2(z[q][k], rgh, (tid + q * T) * 8, k * RS2);
+            const float l = bload(rlam, (tid + q * T) * 4, k * RS);
+            z[q][k].x *= l;
+            z[q][k].y *= l;
+            QDVM_CHUNK_FENCE(k);
+        }
+    inv3d<N, T, Q, RV>(z, xb, tid);             // l(g)
+    float acc[Q][N];                            // holds l(g) until l(f) is formed
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) acc[q][x] = z[q][x].x;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
+            const float l = bload(rlam, (tid + q * T) * 4, k * RS);
+            z[q][k].x *= l;
+            z[q][k].y *= l;
+            QDVM_CHUNK_FENCE(k);
+        }
+    inv3d<N, T, Q, RV>(z, xb, tid);             // l(f)
+    {
+        // M again from the LDS factors (read after the barriers of the transforms)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) {
+                const double m = QDVM_MAXW3(q, x);
+                const float g = (float)((double)bload(cl.f, (tid + q * T) * 4, x * RS) - m);
+                acc[q][x] = -__builtin_fmaf(g, z[q][x].x, (float)m * acc[q][x]);
+            }
+    }
+#undef QDVM_MAXW3
+
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        const float cw = jobw[jb];
+        const float* D = dtab + J.M * N;
+        const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+        const int ds = modc<N>(J.e[2]);
+        float2 tg[Q][N];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const float2 G = bload2(rgh, pi * 8, k * RS2);
+                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
+                tg[q][k] = make_float2(al * G.x - a2 * G.y, al * G.y + a2 * G.x);
+                sidx += ds;
+                sidx -= (sidx >= N) ? N : 0;
+                QDVM_CHUNK_FENCE(k);
+            }
+        }
+        inv3d<N, T, Q, RV>(tg, xb, tid);         // line(g) + i plane(g)
+        if constexpr (STAGE) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                for (int x = 0; x < N; ++x) bstore2(tg[q][x], rtg, (tid + q * T) * 8, x * RS2);
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
+                z[q][k] = make_float2(al * F.x - a2 * F.y, al * F.y + a2 * F.x);
+                sidx += ds;
+                sidx -= (sidx >= N) ? N : 0;
+                QDVM_CHUNK_FENCE(k);
+            }
+        }
+        inv3d<N, T, Q, RV>(z, xb, tid);          // line(f) + i plane(f)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) {
+                const float2 t = STAGE ? bload2(rtg, (tid + q * T) * 8, x * RS2) : tg[q][x];
+                const float gain = __builtin_fmaf(t.x, z[q][x].y, (z[q][x].x - t.x) * t.y);
+                acc[q][x] = __builtin_fmaf(cw, gain, acc[q][x]);
+            }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+            const int v = (tid + q * T) * 4;
+            bstore(dt == 0.f ? acc[q][x] : __builtin_fmaf(dt, acc[q][x], bload(cl.f, v, x * RS)), cl.q, v, x * RS);
+        }
+}
+
 // Adjoint of one cell.  With c the cotangent and unnormalised transforms F:
 //   l + i C(cf) = IFFT(Lambda (fhat + i F(cf)))            (both real)
 //   per job:  u + i v = IFFT((a + i a') fhat) = n^d (g + i h)

@@ -28,8 +28,9 @@
 
 namespace qdvm {
 
-// 256 threads, 256/n cells per workgroup item, persistent over items.
-template <int N, int RV>
+// 256 threads, 256/n cells per workgroup item, persistent over items.  SPLIT
+// selects the near-equilibrium evaluation (second spectral buffer for g).
+template <int N, int RV, bool SPLIT>
 __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const float* f, float* q, float dt,
                                                 DevScratch s)
 {
@@ -47,12 +48,18 @@ __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const flo
     it.fh = make_rsrc(s.spec + (size_t)blockIdx.x * CPB * NPTS, CPB * NPTS * 8);
     it.vcell = (local * NPTS + j) * 4;
     it.vspec = (local * NPTS + j) * 8;
+    // near-equilibrium mode: the spectrum of g per slot (spec2 holds two slot sets; the second, a
+    // staging area, is not needed at 256 threads per block)
+    const rsrc_t rgh = make_rsrc(SPLIT ? s.spec2 + (size_t)blockIdx.x * CPB * NPTS : s.spec, CPB * NPTS * 8);
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int first = item * CPB;
         const int nvalid = min(CPB, batch - first);
         it.f = make_rsrc(f + (size_t)first * NPTS, nvalid * NPTS * 4);
         it.q = make_rsrc(q + (size_t)first * NPTS, nvalid * NPTS * 4);
-        cell2d_eval<N, RV>(pl, it, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
+        if constexpr (SPLIT)
+            cell2d_eval_split<N, RV, false>(pl, it, rgh, rgh, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
+        else
+            cell2d_eval<N, RV>(pl, it, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
     }
 }
 
@@ -99,12 +106,12 @@ template <int N>
 size_t lds2d(int ntilde) { return sizeof(float) * ((size_t)(256 / N) * N * (N + 1) + (size_t)(ntilde + 1) * N); }
 }  // namespace
 
-#define QDVM_SWITCH_2D(N_, BODY)                          \
+#define QDVM_SWITCH_2D(N_, ...)                          \
     switch (N_) {                                          \
-        case 8: { constexpr int N = 8; BODY; } break;      \
-        case 16: { constexpr int N = 16; BODY; } break;    \
-        case 32: { constexpr int N = 32; BODY; } break;    \
-        case 64: { constexpr int N = 64; BODY; } break;    \
+        case 8: { constexpr int N = 8; __VA_ARGS__; } break;      \
+        case 16: { constexpr int N = 16; __VA_ARGS__; } break;    \
+        case 32: { constexpr int N = 32; __VA_ARGS__; } break;    \
+        case 64: { constexpr int N = 64; __VA_ARGS__; } break;    \
         default: return hipErrorInvalidValue;              \
     }
 
@@ -115,8 +122,12 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
         li.block = 256;
         li.lds = lds2d<N>(pl.ntilde);
         const int items = (batch + 256 / N - 1) / (256 / N);
-        e = variant ? occupancy_grid(k_eval2d<N, 1>, 256, li.lds, items, li.grid)
-                    : occupancy_grid(k_eval2d<N, 0>, 256, li.lds, items, li.grid);
+        if (pl.mode)
+            e = variant ? occupancy_grid(k_eval2d<N, 1, true>, 256, li.lds, items, li.grid)
+                        : occupancy_grid(k_eval2d<N, 0, true>, 256, li.lds, items, li.grid);
+        else
+            e = variant ? occupancy_grid(k_eval2d<N, 1, false>, 256, li.lds, items, li.grid)
+                        : occupancy_grid(k_eval2d<N, 0, false>, 256, li.lds, items, li.grid);
         li.slots = li.grid * (256 / N);
     });
     return e;
@@ -126,10 +137,14 @@ hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q,
                          const LaunchInfo& li, int variant, hipStream_t st)
 {
     QDVM_SWITCH_2D(pl.n, {
-        if (variant)
-            hipLaunchKernelGGL((k_eval2d<N, 1>), dim3(li.grid), dim3(256), li.lds, st, pl, batch, f, q, dt, s);
-        else
-            hipLaunchKernelGGL((k_eval2d<N, 0>), dim3(li.grid), dim3(256), li.lds, st, pl, batch, f, q, dt, s);
+        const dim3 g(li.grid), b(256);
+        if (pl.mode) {
+            if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+            else hipLaunchKernelGGL((k_eval2d<N, 0, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+        } else {
+            if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+            else hipLaunchKernelGGL((k_eval2d<N, 0, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+        }
     });
     return hipGetLastError();
 }

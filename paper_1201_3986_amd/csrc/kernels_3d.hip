@@ -28,7 +28,7 @@
 
 namespace qdvm {
 
-template <int N, int T, int RV>
+template <int N, int T, int RV, bool SPLIT>
 __global__ __launch_bounds__(T) void k_eval3d(DevPlan pl, int batch, const float* f, float* q, float dt,
                                               DevScratch s)
 {
@@ -36,16 +36,25 @@ __global__ __launch_bounds__(T) void k_eval3d(DevPlan pl, int batch, const float
     extern __shared__ float smem[];
     float* xb = smem;
     float* dtab = smem + N * N * (N + 1);
+    double* red = (double*)(dtab + (pl.ntilde + 1) * N);
     const int tid = threadIdx.x;
     for (int i = tid; i < (pl.ntilde + 1) * N; i += T) dtab[i] = pl.dirichlet[i];
     __syncthreads();
     const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
     Cell3D cl;
     cl.fh = make_rsrc(s.spec + (size_t)blockIdx.x * NPTS, NPTS * 8);
+    // near-equilibrium mode: spectrum of g, and for n = 32 (two transforms do not fit in the
+    // registers of 512 threads) a staging area for the transform of g of each job
+    constexpr bool STAGE = N == 32;
+    const rsrc_t rgh = make_rsrc(SPLIT ? s.spec2 + (size_t)blockIdx.x * NPTS : s.spec, NPTS * 8);
+    const rsrc_t rtg = make_rsrc(SPLIT ? s.spec2 + (size_t)(gridDim.x + blockIdx.x) * NPTS : s.spec, NPTS * 8);
     for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
         cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
         cl.q = make_rsrc(q + (size_t)cell * NPTS, NPTS * 4);
-        cell3d_eval<N, T, RV>(pl, cl, rlam, s.jobw, dt, xb, dtab, tid);
+        if constexpr (SPLIT)
+            cell3d_eval_split<N, T, RV, STAGE>(pl, cl, rgh, rtg, rlam, s.jobw, dt, xb, red, dtab, tid);
+        else
+            cell3d_eval<N, T, RV>(pl, cl, rlam, s.jobw, dt, xb, dtab, tid);
     }
 }
 
@@ -161,16 +170,16 @@ constexpr int t3d()
 }
 
 template <int N>
-size_t lds3d(int ntilde) { return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)(ntilde + 1) * N + 64); }
+size_t lds3d(int ntilde) { return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)(ntilde + 1) * N + 160); }
 
 }  // namespace
 
-#define QDVM_SWITCH_3D(N_, BODY)                          \
+#define QDVM_SWITCH_3D(N_, ...)                          \
     switch (N_) {                                          \
-        case 8: { constexpr int N = 8; BODY; } break;      \
-        case 16: { constexpr int N = 16; BODY; } break;    \
-        case 24: { constexpr int N = 24; BODY; } break;    \
-        case 32: { constexpr int N = 32; BODY; } break;    \
+        case 8: { constexpr int N = 8; __VA_ARGS__; } break;      \
+        case 16: { constexpr int N = 16; __VA_ARGS__; } break;    \
+        case 24: { constexpr int N = 24; __VA_ARGS__; } break;    \
+        case 32: { constexpr int N = 32; __VA_ARGS__; } break;    \
         default: return hipErrorInvalidValue;              \
     }
 
@@ -194,8 +203,12 @@ LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant)
                 constexpr int T = t3d<N>();
                 li.block = T;
                 li.lds = lds3d<N>(pl.ntilde);
-                e = variant ? occupancy_grid(k_eval3d<N, T, 1>, T, li.lds, batch, li.grid)
-                            : occupancy_grid(k_eval3d<N, T, 0>, T, li.lds, batch, li.grid);
+                if (pl.mode)
+                    e = variant ? occupancy_grid(k_eval3d<N, T, 1, true>, T, li.lds, batch, li.grid)
+                                : occupancy_grid(k_eval3d<N, T, 0, true>, T, li.lds, batch, li.grid);
+                else
+                    e = variant ? occupancy_grid(k_eval3d<N, T, 1, false>, T, li.lds, batch, li.grid)
+                                : occupancy_grid(k_eval3d<N, T, 0, false>, T, li.lds, batch, li.grid);
                 li.slots = li.grid;
             });
             return e;
@@ -212,10 +225,14 @@ hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, f
     if (pl.dim == 2) return launch_eval2d(pl, batch, f, q, dt, s, li, variant, st);
     QDVM_SWITCH_3D(pl.n, {
         constexpr int T = t3d<N>();
-        if (variant)
-            hipLaunchKernelGGL((k_eval3d<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, q, dt, s);
-        else
-            hipLaunchKernelGGL((k_eval3d<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, q, dt, s);
+        const dim3 g(li.grid), b(T);
+        if (pl.mode) {
+            if (variant) hipLaunchKernelGGL((k_eval3d<N, T, 1, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+            else hipLaunchKernelGGL((k_eval3d<N, T, 0, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+        } else {
+            if (variant) hipLaunchKernelGGL((k_eval3d<N, T, 1, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+            else hipLaunchKernelGGL((k_eval3d<N, T, 0, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+        }
     });
     return hipGetLastError();
 }

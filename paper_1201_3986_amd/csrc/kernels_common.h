@@ -61,6 +61,15 @@ __device__ __forceinline__ void bstore2(float2 x, rsrc_t r, int voff, int soff)
     __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
 }
 
+// The value unchanged, but opaque to the optimiser (no instruction is emitted):
+// stops it from reusing an expensive expression across a long stretch of code
+// where keeping the result alive would cost registers.
+__device__ __forceinline__ double opaque(double v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 template <int N>
 __device__ __forceinline__ int modc(int x)
 {

@@ -23,6 +23,7 @@ struct JobDesc {
 struct DevPlan {
     int32_t dim, n, ntilde, P, njobs;
     int32_t npts;                // n^dim
+    int32_t mode;                // 0: Q(f, f); 1: near-equilibrium Q(f, f) - Q(M, M)
     const JobDesc* jobs;         // [njobs]
     const float* dirichlet;      // [(ntilde+1) * n]: D_M(s) = sum_{|m|<=M} cos(2 pi m s / n)
     const float* aperp;          // 3D: [njobs][npts] plane multipliers, spectral layout; 2D: null
@@ -37,14 +38,14 @@ struct DevScratch {
     float* lam;      // [npts]  loss multiplier Lambda / npts, spectral layout
     float* jobw;     // [njobs] combined job weight / npts^2
     float2* spec;    // [slots * npts] spectrum of f per resident cell slot
-    float2* spec2;   // [slots * npts] second spectral buffer (adjoint)
+    float2* spec2;   // [slots * npts] second spectral buffer (adjoint; g in near-equilibrium mode)
     float2* acc;     // [slots * npts] spectral accumulator (adjoint)
     float* gw_part;  // [batch * njobs] per-cell job partials of grad_w (adjoint)
     int32_t* counter;  // work-queue counter (batched)
 };
 
 struct HostPlan {
-    int32_t dim = 0, n = 0, ntilde = 0, P = 0;
+    int32_t dim = 0, n = 0, ntilde = 0, P = 0, mode = 0;
     double half_width = 0, h = 0;
     std::vector<int32_t> dirs;       // P * dim
     std::vector<double> weights;     // P
@@ -72,6 +73,7 @@ struct HostPlan {
         DevPlan d;
         d.dim = dim; d.n = n; d.ntilde = ntilde; d.P = P; d.njobs = (int32_t)jobs.size();
         d.npts = npts();
+        d.mode = mode;
         d.jobs = d_jobs; d.dirichlet = d_dirichlet; d.aperp = d_aperp; d.w_default = d_w;
         d.dir_job = d_dir_job;
         d.lam0 = d_lam0;
@@ -128,11 +130,14 @@ struct BatchDev {
     int32_t* counter;
     float2* spec;              // [grid][slot_elems]
     int64_t slot_elems;
+    int64_t gslot;             // near-equilibrium plans: the spectrum of g at slot + gslot and a staging
+                               // area at slot + 2 gslot (slot_elems = 3 gslot); else 0
     uint32_t fbytes;           // extent of f and q in bytes
     int32_t dtab_floats;       // LDS floats reserved for the Dirichlet table
 };
 
-hipError_t batched_launch_info(int family, int nitems, LaunchInfo& li, size_t dtab_floats);
+// dtab_floats must be even (the reduction area after the LDS buffers holds doubles)
+hipError_t batched_launch_info(int family, int nitems, bool split, LaunchInfo& li, size_t dtab_floats);
 size_t batched_slot_elems(int family);
 hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, const float* f, float* q, float dt,
                           hipStream_t st);

@@ -17,6 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libqdvm.so")
 
 QDVM_OK, QDVM_EINVAL, QDVM_EUNSUPPORTED, QDVM_ENOMEM, QDVM_EDEVICE = 0, -1, -2, -3, -4
+MODE_FULL, MODE_NEAR_EQUILIBRIUM = 0, 1
+ABI_VERSION = 2
+_MODES = {"full": MODE_FULL, "near_equilibrium": MODE_NEAR_EQUILIBRIUM}
 
 _lock = threading.Lock()
 _lib = None
@@ -31,12 +34,14 @@ class QdvmError(RuntimeError):
 class Desc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("half_width", ctypes.c_double),
                 ("ntilde", ctypes.c_int32), ("farey_order", ctypes.c_int32), ("num_dirs", ctypes.c_int32),
-                ("dirs", ctypes.POINTER(ctypes.c_int32)), ("weights", ctypes.POINTER(ctypes.c_double))]
+                ("dirs", ctypes.POINTER(ctypes.c_int32)), ("weights", ctypes.POINTER(ctypes.c_double)),
+                ("mode", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("ntilde", ctypes.c_int32),
-                ("num_dirs", ctypes.c_int32), ("num_jobs", ctypes.c_int32), ("h", ctypes.c_double)]
+                ("num_dirs", ctypes.c_int32), ("num_jobs", ctypes.c_int32), ("h", ctypes.c_double),
+                ("mode", ctypes.c_int32)]
 
 
 def load():
@@ -78,6 +83,9 @@ def load():
         lib.qdvm_status_string.restype = ctypes.c_char_p
         lib.qdvm_last_error.restype = ctypes.c_char_p
         lib.qdvm_abi_version.restype = ctypes.c_int32
+        if lib.qdvm_abi_version() != ABI_VERSION:
+            raise ImportError("libqdvm.so has ABI %d, the binding expects %d; rebuild it"
+                              % (lib.qdvm_abi_version(), ABI_VERSION))
         _lib = lib
         return lib
 
@@ -88,9 +96,17 @@ def _check(status: int):
         raise QdvmError(status, lib.qdvm_last_error().decode() or lib.qdvm_status_string(status).decode())
 
 
-def _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights):
+def _mode(mode):
+    if isinstance(mode, str):
+        if mode not in _MODES:
+            raise ValueError("mode must be one of %s" % sorted(_MODES))
+        return _MODES[mode]
+    return int(mode)
+
+
+def _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights, mode=MODE_FULL):
     keep = []
-    d = Desc(dim, n, float(half_width), ntilde, farey_order, num_dirs, None, None)
+    d = Desc(dim, n, float(half_width), ntilde, farey_order, num_dirs, None, None, _mode(mode))
     if dirs is not None:
         a = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1, dim))
         keep.append(a)
@@ -132,9 +148,12 @@ def _ptr(t):
 class Plan:
     """An immutable plan (directions, weights, multiplier tables) on the current device."""
 
-    def __init__(self, dim, n, half_width=8.0, ntilde=0, farey_order=0, num_dirs=0, dirs=None, weights=None):
+    def __init__(self, dim, n, half_width=8.0, ntilde=0, farey_order=0, num_dirs=0, dirs=None, weights=None,
+                 mode=MODE_FULL):
+        """mode: "full" (Q(f, f)) or "near_equilibrium" (Q(f, f) - Q(M, M) with M
+        the cell's Maxwellian, evaluated as Q(g, f) + Q(M, g), g = f - M)."""
         lib = load()
-        d, keep = _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights)
+        d, keep = _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights, mode)
         h = ctypes.c_void_p()
         _check(lib.qdvm_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -142,6 +161,7 @@ class Plan:
         _check(lib.qdvm_plan_info(h, ctypes.byref(info)))
         self.dim, self.n, self.ntilde = info.dim, info.n, info.ntilde
         self.num_dirs, self.num_jobs, self.h = info.num_dirs, info.num_jobs, info.h
+        self.mode = info.mode
         self.npts = self.n ** self.dim
         self.dirs = np.zeros((self.num_dirs, dim), dtype=np.int32)
         self.weights = np.zeros(self.num_dirs, dtype=np.float64)

@@ -187,3 +187,76 @@ def test_config4_graph_step(gpu_lib):
     # plain FP32 cannot reach 1e-5 of max|Q| on these near-equilibrium cells
     # (gain and loss are 50-100x larger than Q); the near-equilibrium mode does.
     assert max(errs) <= 1e-4
+
+
+def test_config4_graph_step_near_equilibrium(gpu_lib):
+    """The batched inhomogeneous workload in the near-equilibrium mode: every
+    sampled cell within 1e-5 of max|Q| of the oracle's Q(f, f), replays equal
+    to the eager step, and plain and near-equilibrium plans mixed in one batch
+    give the single-plan results bit for bit."""
+    import torch
+    import oracle
+    wl = workloads.c4()
+    c2, c3 = wl["classes"]
+    near = "near_equilibrium"
+    p2 = gpu_lib.Plan(2, 32, 8.0, num_dirs=16, mode=near)
+    p3 = gpu_lib.Plan(3, 24, 8.0, num_dirs=16, mode=near)
+    f2, f3 = c2["f"].reshape(len(c2["f"]), -1), c3["f"].reshape(len(c3["f"]), -1)
+    plans = [p2] * len(f2) + [p3] * len(f3)
+    offs = np.concatenate([np.arange(len(f2)) * 1024, len(f2) * 1024 + np.arange(len(f3)) * 13824]).astype(np.int64)
+    flat = np.concatenate([f2.reshape(-1), f3.reshape(-1)]).astype(np.float32)
+    b = gpu_lib.BatchPlan(plans, offs)
+    dt = wl["dt"]
+    ref = _dev(flat)
+    eager = []
+    for _ in range(2):
+        b.eval(ref, out=ref, dt=dt)
+        torch.cuda.synchronize()
+        eager.append(ref.cpu().numpy())
+    x = _dev(flat)
+    s = torch.cuda.Stream()
+    g = gpu_lib.StepGraph(b, x, dt, s)
+    for k in range(2):
+        g.launch(stream=s)
+        s.synchronize()
+        scratch = torch.ones(1 << 20, device="cuda") * 3.0
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), eager[k]), k
+        del scratch
+    q = b.eval(_dev(flat))
+    torch.cuda.synchronize()
+    qn = q.cpu().numpy()
+    # same cells through the single-plan kernels
+    q2 = p2.eval(_dev(f2))
+    q3 = p3.eval(_dev(f3))
+    torch.cuda.synchronize()
+    assert np.array_equal(qn[:len(f2) * 1024], q2.cpu().numpy().reshape(-1))
+    assert np.array_equal(qn[len(f2) * 1024:], q3.cpu().numpy().reshape(-1))
+    errs, errs_def = [], []
+    for i in list(range(0, len(f2), 512)) + [len(f2), len(f2) + 511]:
+        o, plan = offs[i], plans[i]
+        cell = flat[o:o + plan.npts]
+        w = np.float32(plan.weights).astype(np.float64)
+        full = oracle.collide(plan.dim, plan.n, plan.ntilde, plan.dirs, w, cell.astype(np.float64))
+        defn = oracle.collide_near_equilibrium(plan.dim, plan.n, plan.ntilde, plan.dirs, w, cell.astype(np.float64))
+        errs.append(rel_linf(qn[o:o + plan.npts], full))
+        errs_def.append(rel_linf(qn[o:o + plan.npts], defn))
+    print("config4 near-eq: sampled rel errors vs Q(f,f): %s" % " ".join("%.2e" % e for e in errs))
+    print("config4 near-eq: sampled rel errors vs definition: %s" % " ".join("%.2e" % e for e in errs_def))
+    assert max(errs) <= TOL
+    assert max(errs_def) <= TOL
+    # mixed batch: plain and near-equilibrium plans of both families together
+    pf2 = gpu_lib.Plan(2, 32, 8.0, num_dirs=16)
+    p64 = gpu_lib.Plan(2, 64, 8.0, num_dirs=8, mode=near)
+    rng = np.random.default_rng(5)
+    cells = [(p2, f2[0]), (pf2, f2[1]), (p3, f3[0]), (p64, workloads.noisy_local_maxwellian(rng, 2, 64, 8.0)),
+             (pf2, f2[2]), (p2, f2[3])]
+    mflat, moffs = _layout(cells)
+    mb = gpu_lib.BatchPlan([c[0] for c in cells], moffs)
+    mq = mb.eval(_dev(mflat))
+    torch.cuda.synchronize()
+    mq = mq.cpu().numpy()
+    for (plan, a), o in zip(cells, moffs):
+        single = plan.eval(_dev(a.reshape(1, -1)))
+        torch.cuda.synchronize()
+        assert np.array_equal(mq[o:o + plan.npts], single.cpu().numpy().reshape(-1))

@@ -1,0 +1,153 @@
+"""GPU parity of the near-equilibrium evaluation mode.
+
+The mode returns Q(f, f) - Q(M, M), M the index-grid Maxwellian of each cell
+(oracle.index_maxwellian), evaluated on the GPU as Q(g, f) + Q(M, g) with
+g = f - M.  Its oracle is the definition written out by direct summation,
+oracle.collide_near_equilibrium.  On the batched inhomogeneous workload
+(noisy local Maxwellians, 2D n = 32 and 3D n = 24) the dropped Q(M, M) is only
+the periodic-wrap residue of the Maxwellian, at most ~1e-6 of max|Q|, so the
+result also meets the 1e-5 bar against the oracle's plain Q(f, f), which the
+plain FP32 mode does not on these cells.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_3986_amd import workloads
+from parity_util import oracle_q, per_cell_rel_linf, rel_linf
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+NEAR = "near_equilibrium"
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _eval(plan, f, **kw):
+    import torch
+    out = plan.eval(_dev(f), **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_near(plan, f32, w=None):
+    weights = np.float32(plan.weights if w is None else w).astype(np.float64)
+    return oracle.collide_near_equilibrium(plan.dim, plan.n, plan.ntilde, plan.dirs, weights,
+                                           np.asarray(f32, np.float32).astype(np.float64))
+
+
+def _local_maxwellians(seed, d, n, cells, noise=0.02, R=8.0):
+    rng = np.random.default_rng(seed)
+    return np.stack([workloads.noisy_local_maxwellian(rng, d, n, R, noise) for _ in range(cells)]).astype(np.float32)
+
+
+def test_mode_reported_and_invalid_mode_rejected(gpu_lib):
+    p = gpu_lib.Plan(2, 16, 8.0, num_dirs=8, mode=NEAR)
+    assert p.mode == gpu_lib.MODE_NEAR_EQUILIBRIUM
+    assert gpu_lib.Plan(2, 16, 8.0, num_dirs=8).mode == gpu_lib.MODE_FULL
+    with pytest.raises(gpu_lib.QdvmError) as ei:
+        gpu_lib.Plan(2, 16, 8.0, num_dirs=8, mode=7)
+    assert ei.value.status == gpu_lib.QDVM_EINVAL
+    with pytest.raises(ValueError):
+        gpu_lib.Plan(2, 16, 8.0, num_dirs=8, mode="nearly")
+
+
+@pytest.mark.parametrize("d,n,P,cells", [(2, 32, 16, 37), (3, 24, 16, 3)])
+def test_config4_classes_single_plan(gpu_lib, d, n, P, cells):
+    f = _local_maxwellians(404 + d, d, n, cells)
+    near = gpu_lib.Plan(d, n, 8.0, num_dirs=P, mode=NEAR)
+    full = gpu_lib.Plan(d, n, 8.0, num_dirs=P)
+    qn = _eval(near, f)
+    qf = _eval(full, f)
+    ref_near = oracle_near(near, f)
+    ref_full = oracle_q(full, f)
+    e_def = per_cell_rel_linf(qn, ref_near, n ** d)
+    e_q = per_cell_rel_linf(qn, ref_full, n ** d)
+    e_plain = per_cell_rel_linf(qf, ref_full, n ** d)
+    print("d=%d n=%d: near-eq vs its definition %.2e, vs Q(f,f) %.2e; plain FP32 vs Q(f,f) %.2e"
+          % (d, n, e_def.max(), e_q.max(), e_plain.max()))
+    assert e_def.max() <= TOL
+    assert e_q.max() <= TOL
+
+
+@pytest.mark.parametrize("d,n,P,cells", [
+    (2, 8, 4, 9), (2, 16, 8, 21), (2, 32, 13, 9), (2, 64, 16, 5),
+    (3, 8, 7, 3), (3, 16, 16, 2), (3, 24, 9, 2), (3, 32, 16, 2),
+])
+def test_all_sizes_against_definition(gpu_lib, d, n, P, cells):
+    # several workgroup items with a ragged tail.  n = 8 uses the box [-4, 4)^d:
+    # on [-8, 8)^d (h = 2) these temperatures put a cell on a handful of points,
+    # where Q is ~1e-4 of the terms that cancel in it and FP32 cannot resolve it
+    # in either mode
+    R = 4.0 if n == 8 else 8.0
+    f = _local_maxwellians(500 + n + d, d, n, cells, R=R)
+    plan = gpu_lib.Plan(d, n, R, num_dirs=P, mode=NEAR)
+    q = _eval(plan, f)
+    errs = per_cell_rel_linf(q, oracle_near(plan, f), n ** d)
+    print("d=%d n=%d P=%d: max cell rel err %.3e" % (d, n, P, errs.max()))
+    assert errs.max() <= TOL
+
+
+def test_far_from_equilibrium_still_exact_identity(gpu_lib):
+    # the bilinear identity holds for every f: two separated Maxwellians
+    f = workloads.two_maxwellians_batch(11, 6, 64, noise=0.05)
+    plan = gpu_lib.Plan(2, 64, 8.0, num_dirs=16, mode=NEAR)
+    q = _eval(plan, f)
+    errs = per_cell_rel_linf(q, oracle_near(plan, f), 64 * 64)
+    print("two Maxwellians: %.3e" % errs.max())
+    assert errs.max() <= TOL
+
+
+def test_degenerate_cells_fall_back_to_full(gpu_lib):
+    # zero mass, negative mass and three neighbouring spikes (index temperature
+    # 3/16 <= 1/4): no usable Maxwellian, M = 0
+    n = 16
+    f = np.zeros((4, n, n), np.float32)
+    f[1] = -workloads.random_positive(3, 2, n, 1)[0]
+    f[2, 5, 7] = 2.0
+    f[2, 5, 8] = 1.0
+    f[2, 6, 7] = 1.0
+    f[3] = workloads.random_positive(4, 2, n, 1)[0]
+    near = gpu_lib.Plan(2, n, 8.0, num_dirs=8, mode=NEAR)
+    full = gpu_lib.Plan(2, n, 8.0, num_dirs=8)
+    q = _eval(near, f)
+    assert np.all(q[0] == 0.0)
+    ref = oracle_near(near, f).reshape(4, -1)
+    for c in (1, 2):
+        assert np.all(oracle.index_maxwellian(2, n, f[c]) == 0.0)
+        assert rel_linf(q[c], ref[c]) <= TOL
+        assert rel_linf(q[c], oracle_q(full, f[c])) <= TOL
+    assert rel_linf(q[3], ref[3]) <= TOL
+
+
+def test_euler_in_place_and_call_weights(gpu_lib):
+    import torch
+    f = _local_maxwellians(77, 2, 32, 10)
+    plan = gpu_lib.Plan(2, 32, 8.0, num_dirs=16, mode=NEAR)
+    dt = 0.01
+    ref = f.astype(np.float64) + dt * oracle_near(plan, f).reshape(f.shape)
+    x = _dev(f)
+    plan.eval(x, out=x, dt=dt)
+    torch.cuda.synchronize()
+    assert rel_linf(x.cpu().numpy(), ref) <= 1e-6
+    rng = np.random.default_rng(8)
+    w = rng.uniform(0.5, 2.0, size=plan.num_dirs).astype(np.float32)
+    q = plan.eval(_dev(f), w=_dev(w))
+    torch.cuda.synchronize()
+    errs = per_cell_rel_linf(q.cpu().numpy(), oracle_near(plan, f, w=w), 32 * 32)
+    assert errs.max() <= TOL
+
+
+def test_mass_conservation(gpu_lib):
+    # both bilinear terms conserve mass (Prop. 3.3 holds for Q(a, b) as well)
+    f = _local_maxwellians(91, 3, 24, 2)
+    plan = gpu_lib.Plan(3, 24, 8.0, num_dirs=16, mode=NEAR)
+    q = _eval(plan, f).reshape(2, -1).astype(np.float64)
+    ref = oracle_near(plan, f).reshape(2, -1)
+    for c in range(2):
+        res = abs(q[c].sum()) / np.sum(np.abs(ref[c]))
+        print("mass residual %.3e" % res)
+        assert res <= 1e-6
