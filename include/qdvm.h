@@ -159,7 +159,7 @@ qdvm_status qdvm_vjp(qdvm_plan_t plan, int32_t batch, const float* f, const floa
 /*
  * Heterogeneous batch: many spatial cells, each with its own plan (grid size,
  * direction set, weights), evaluated in one persistent launch per block-size
- * family present (family A: 2D n = 8, 16, 32 and 3D n = 24; family B: 2D
+ * family present (256 threads: 2D n = 8, 16, 32; 576: 3D n = 24; 512: 2D
  * n = 64 and 3D n = 32), with a device work queue ordered by cost.  Sec. 3.3
  * notes that the direction set may vary with position; each cell is the
  * single-cell operator of its plan.

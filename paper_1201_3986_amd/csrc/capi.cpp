@@ -246,14 +246,18 @@ int batch_class(int dim, int n)
     return -1;
 }
 
-int class_family(int c) { return (c == qdvm::BC_2D64 || c == qdvm::BC_3D32) ? qdvm::BF_512 : qdvm::BF_576; }
+int class_family(int c)
+{
+    if (c == qdvm::BC_2D64 || c == qdvm::BC_3D32) return qdvm::BF_512;
+    return c == qdvm::BC_3D24 ? qdvm::BF_576 : qdvm::BF_256;
+}
 
 int class_cells_per_item(int c)
 {
     switch (c) {
-        case qdvm::BC_2D8: return 576 / 8;
-        case qdvm::BC_2D16: return 576 / 16;
-        case qdvm::BC_2D32: return 576 / 32;
+        case qdvm::BC_2D8: return 256 / 8;
+        case qdvm::BC_2D16: return 256 / 16;
+        case qdvm::BC_2D32: return 256 / 32;
         case qdvm::BC_2D64: return 512 / 64;
         default: return 1;
     }
@@ -521,7 +525,7 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
     b->ncells = ncells;
     b->fbytes = (uint32_t)(max_end * 4);
     b->flops = flops;
-    for (int fam = 0; fam < 2; ++fam) {
+    for (int fam = 0; fam < qdvm::kNumFamilies; ++fam) {
         // groups of cells with the same (class, plan), in order of first appearance
         std::vector<std::pair<std::pair<int, const qdvm_plan_s*>, std::vector<int32_t>>> groups;
         for (int32_t c = 0; c < ncells; ++c) {
@@ -556,7 +560,7 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
                 slot = (int)plan_of_slot.size();
                 plan_of_slot.push_back(p);
                 F.plans.push_back(p->hp.dev());
-                dtab_floats = std::max<size_t>(dtab_floats, (size_t)(p->hp.ntilde + 1) * p->hp.n);
+                dtab_floats = std::max<size_t>(dtab_floats, (size_t)2 * (p->hp.ntilde + 1) * p->hp.n);
                 any_split = any_split || p->hp.mode == QDVM_MODE_NEAR_EQUILIBRIUM;
             }
             const int cpi = class_cells_per_item(cls);
@@ -570,11 +574,16 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
                 tmp.push_back(t);
             }
         }
-        // most expensive items first, so the tail of the queue is made of small ones
-        std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& c) { return a.cost > c.cost; });
+        // grouped by class (one queue each); within a class the most expensive
+        // items first, so that the tail of each queue is made of small ones
+        std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& c) {
+            return a.it.cls != c.it.cls ? a.it.cls < c.it.cls : a.cost > c.cost;
+        });
+        for (int k = 0; k < qdvm::kNumClasses; ++k) F.dev.cls_first[k] = F.dev.cls_count[k] = 0;
         for (auto& t : tmp) {
             t.it.first = (int32_t)F.cell_off.size();
             for (int32_t c : t.cells) F.cell_off.push_back(cell_offset[c]);
+            if (F.dev.cls_count[t.it.cls]++ == 0) F.dev.cls_first[t.it.cls] = (int32_t)F.items.size();
             F.items.push_back(t.it);
         }
         dtab_floats = (dtab_floats + 1) & ~size_t(1);
@@ -592,7 +601,7 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
         if (e == hipSuccess) e = hipMemcpy(F.d_cell_off, F.cell_off.data(), sizeof(int64_t) * F.cell_off.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMalloc(&F.d_plans, sizeof(qdvm::DevPlan) * F.plans.size());
         if (e == hipSuccess) e = hipMemcpy(F.d_plans, F.plans.data(), sizeof(qdvm::DevPlan) * F.plans.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMalloc(&F.d_counter, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&F.d_counter, sizeof(int32_t) * qdvm::kNumClasses);
         if (e == hipSuccess) e = hipMalloc(&F.d_spec, sizeof(float2) * slot_elems * F.li.grid);
         if (e != hipSuccess) {
             b->fams.push_back(F);

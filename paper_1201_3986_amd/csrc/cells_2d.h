@@ -100,6 +100,31 @@ struct Item2D {
     int vspec;           // byte offset of this lane's pencil in spectral arrays (float2)
 };
 
+// z = (alpha + i alpha') * spectrum for one job, the spectrum read from the
+// slot rs at the lane's pencil.  alpha(K) = D_M(e.K) - 1 and alpha'(K) =
+// D_M(e_perp.K) walk one row each of the LDS tables: along the lane's row
+// K0 = j their arguments advance by e_1 and e_0 per element (K1).  (The job
+// weight is applied to the product, not folded into alpha: the real and
+// imaginary parts of one complex transform must be of the same size, or the
+// rounding of the larger one swamps the smaller.)
+template <int N>
+__device__ __forceinline__ void job2d_multiply(float2 (&z)[N], rsrc_t rs, int vspec, const JobDesc& J,
+                                               const float* dtab, const float* atab, int j)
+{
+    constexpr int RS2 = N * 8;
+    RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * j), modc<N>(J.e[1]));
+    RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float2 F = bload2(rs, vspec, k * RS2);
+        const float al = a.get(), ap = b.get();
+        z[k] = make_float2(__builtin_fmaf(al, F.x, -ap * F.y), __builtin_fmaf(al, F.y, ap * F.x));
+        a.next();
+        b.next();
+        QDVM_CHUNK_FENCE(k);
+    }
+}
+
 template <int N, int RV>
 __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it, rsrc_t rlam,
                                             const float* __restrict__ jobw, float dt, bool valid, float* xb,
@@ -126,18 +151,11 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
     for (int i = 0; i < N; ++i) acc[i] = -bload(it.f, it.vcell, i * RS) * z[i].x;
 
     // direction loop: g + i h = IFFT((alpha + i alpha') fhat), acc += W g h
+    const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = pl.jobs[jb];
         const float cw = jobw[jb];
-        Mult2D m = mult2d_init<N>(J, dtab, j);
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const float2 F = bload2(it.fh, it.vspec, k * RS2);
-            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
-            z[k] = make_float2(al * F.x - ap * F.y, al * F.y + ap * F.x);
-            mult2d_step<N>(m);
-            QDVM_CHUNK_FENCE(k);
-        }
+        job2d_multiply<N>(z, it.fh, it.vspec, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);
 #pragma unroll
         for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
@@ -253,33 +271,18 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
     }
 #undef QDVM_MAXW
 
+    const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = pl.jobs[jb];
         const float cw = jobw[jb];
         float2 tg[N];
-        Mult2D m = mult2d_init<N>(J, dtab, j);
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const float2 G = bload2(rgh, it.vspec, k * RS2);
-            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
-            tg[k] = make_float2(al * G.x - ap * G.y, al * G.y + ap * G.x);
-            mult2d_step<N>(m);
-            QDVM_CHUNK_FENCE(k);
-        }
+        job2d_multiply<N>(tg, rgh, it.vspec, J, dtab, atab, j);
         inv2d<N, RV>(tg, xb, j);                 // line(g) + i plane(g)
         if constexpr (STAGE) {
 #pragma unroll
             for (int i = 0; i < N; ++i) bstore2(tg[i], rtg, it.vspec, i * RS2);
         }
-        m = mult2d_init<N>(J, dtab, j);
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const float2 F = bload2(it.fh, it.vspec, k * RS2);
-            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
-            z[k] = make_float2(al * F.x - ap * F.y, al * F.y + ap * F.x);
-            mult2d_step<N>(m);
-            QDVM_CHUNK_FENCE(k);
-        }
+        job2d_multiply<N>(z, it.fh, it.vspec, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);                  // line(f) + i plane(f)
 #pragma unroll
         for (int i = 0; i < N; ++i) {

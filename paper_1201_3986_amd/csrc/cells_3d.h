@@ -90,6 +90,32 @@ struct Cell3D {
     rsrc_t f, q, fh;
 };
 
+// z = (alpha + i alpha') * spectrum for one job (spectral layout: lane pencil
+// pi = Kx n + Ky, element k = Kz).  alpha(K) = D_M(e.K) - 1 walks one row of
+// the LDS table (its argument advances by e_2 per element); alpha' is the job's
+// FP64-built plane table.  The job weight is applied to the product (see
+// job2d_multiply).
+template <int N, int T, int Q>
+__device__ __forceinline__ void job3d_multiply(float2 (&z)[Q][N], rsrc_t rs, const DevPlan& pl, const JobDesc& J,
+                                               int jb, const float* atab, int tid)
+{
+    constexpr int NN = N * N, RS = NN * 4, RS2 = NN * 8;
+    const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+        RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const float2 F = bload2(rs, pi * 8, k * RS2);
+            const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
+            z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
+            a.next();
+            QDVM_CHUNK_FENCE(k);
+        }
+    }
+}
+
 template <int N, int T, int RV>
 __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl, rsrc_t rlam,
                                             const float* __restrict__ jobw, float dt, float* xb,
@@ -119,26 +145,11 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 #pragma unroll
         for (int x = 0; x < N; ++x) acc[q][x] = -bload(cl.f, (tid + q * T) * 4, x * RS) * z[q][x].x;
 
+    const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = pl.jobs[jb];
         const float cw = jobw[jb];
-        const float* D = dtab + J.M * N;
-        const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
-        const int ds = modc<N>(J.e[2]);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
-            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
-                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
-                z[q][k] = make_float2(al * F.x - a2 * F.y, al * F.y + a2 * F.x);
-                sidx += ds;
-                sidx -= (sidx >= N) ? N : 0;
-                QDVM_CHUNK_FENCE(k);
-            }
-        }
+        job3d_multiply<N, T, Q>(z, cl.fh, pl, J, jb, atab, tid);
         inv3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
         for (int q = 0; q < Q; ++q)
@@ -278,27 +289,12 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
     }
 #undef QDVM_MAXW3
 
+    const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = pl.jobs[jb];
         const float cw = jobw[jb];
-        const float* D = dtab + J.M * N;
-        const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
-        const int ds = modc<N>(J.e[2]);
         float2 tg[Q][N];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
-            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const float2 G = bload2(rgh, pi * 8, k * RS2);
-                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
-                tg[q][k] = make_float2(al * G.x - a2 * G.y, al * G.y + a2 * G.x);
-                sidx += ds;
-                sidx -= (sidx >= N) ? N : 0;
-                QDVM_CHUNK_FENCE(k);
-            }
-        }
+        job3d_multiply<N, T, Q>(tg, rgh, pl, J, jb, atab, tid);
         inv3d<N, T, Q, RV>(tg, xb, tid);         // line(g) + i plane(g)
         if constexpr (STAGE) {
 #pragma unroll
@@ -306,20 +302,7 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
 #pragma unroll
                 for (int x = 0; x < N; ++x) bstore2(tg[q][x], rtg, (tid + q * T) * 8, x * RS2);
         }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
-            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
-                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
-                z[q][k] = make_float2(al * F.x - a2 * F.y, al * F.y + a2 * F.x);
-                sidx += ds;
-                sidx -= (sidx >= N) ? N : 0;
-                QDVM_CHUNK_FENCE(k);
-            }
-        }
+        job3d_multiply<N, T, Q>(z, cl.fh, pl, J, jb, atab, tid);
         inv3d<N, T, Q, RV>(z, xb, tid);          // line(f) + i plane(f)
 #pragma unroll
         for (int q = 0; q < Q; ++q)

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const flo
     const int j = lane % N, local = wave * CPW + lane / N;
     float* xb = smem + local * SLOT;
     float* dtab = smem + CPB * SLOT;
-    for (int i = tid; i < (pl.ntilde + 1) * N; i += blockDim.x) dtab[i] = pl.dirichlet[i];
+    load_dtab(dtab, pl, tid, blockDim.x);
     __syncthreads();
     const int nitems = (batch + CPB - 1) / CPB;
     const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const floa
     const int j = lane % N, local = wave * CPW + lane / N;
     float* xb = smem + local * SLOT;
     float* dtab = smem + CPB * SLOT;
-    for (int i = tid; i < (pl.ntilde + 1) * N; i += blockDim.x) dtab[i] = pl.dirichlet[i];
+    load_dtab(dtab, pl, tid, blockDim.x);
     __syncthreads();
     const int nitems = (batch + CPB - 1) / CPB;
     const float inv_n = 1.f / (float)NPTS;
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const floa
 // ------------------------------------------------------------------ dispatch
 namespace {
 template <int N>
-size_t lds2d(int ntilde) { return sizeof(float) * ((size_t)(256 / N) * N * (N + 1) + (size_t)(ntilde + 1) * N); }
+size_t lds2d(int ntilde) { return sizeof(float) * ((size_t)(256 / N) * N * (N + 1) + (size_t)2 * (ntilde + 1) * N); }
 }  // namespace
 
 #define QDVM_SWITCH_2D(N_, ...)                          \

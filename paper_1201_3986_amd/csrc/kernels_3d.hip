@@ -36,9 +36,9 @@ __global__ __launch_bounds__(T) void k_eval3d(DevPlan pl, int batch, const float
     extern __shared__ float smem[];
     float* xb = smem;
     float* dtab = smem + N * N * (N + 1);
-    double* red = (double*)(dtab + (pl.ntilde + 1) * N);
+    double* red = (double*)(dtab + dtab_floats(pl));
     const int tid = threadIdx.x;
-    for (int i = tid; i < (pl.ntilde + 1) * N; i += T) dtab[i] = pl.dirichlet[i];
+    load_dtab(dtab, pl, tid, T);
     __syncthreads();
     const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
     Cell3D cl;
@@ -67,9 +67,9 @@ __global__ __launch_bounds__(T) void k_vjp3d(DevPlan pl, int batch, const float*
     extern __shared__ float smem[];
     float* xb = smem;
     float* dtab = smem + N * N * (N + 1);
-    float* red = dtab + (pl.ntilde + 1) * N;
+    float* red = dtab + dtab_floats(pl);
     const int tid = threadIdx.x;
-    for (int i = tid; i < (pl.ntilde + 1) * N; i += T) dtab[i] = pl.dirichlet[i];
+    load_dtab(dtab, pl, tid, T);
     __syncthreads();
     const size_t slot = (size_t)blockIdx.x * NPTS;
     const float inv_n = 1.f / (float)NPTS;
@@ -170,7 +170,7 @@ constexpr int t3d()
 }
 
 template <int N>
-size_t lds3d(int ntilde) { return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)(ntilde + 1) * N + 160); }
+size_t lds3d(int ntilde) { return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)2 * (ntilde + 1) * N + 160); }
 
 }  // namespace
 

@@ -1,5 +1,5 @@
-// Heterogeneous batch (gfx950): cells of different grid sizes and plans in one
-// persistent launch, with an optional forward-Euler epilogue q = f + dt Q.
+// Heterogeneous batch (gfx950): cells of different grid sizes and plans in
+// persistent launches, with an optional forward-Euler epilogue q = f + dt Q.
 //
 // Spatially inhomogeneous kinetic codes apply the collision operator in every
 // spatial cell, and the direction set may vary with position (Sec. 3.3, the
@@ -9,7 +9,8 @@
 // each resident workgroup pops items from an atomic counter until the queue
 // is empty, and runs the same per-cell device code as the uniform kernels.
 // One launch covers every class of one block-size family:
-//   576 threads: 2D n = 8, 16, 32 and 3D n = 24
+//   256 threads: 2D n = 8, 16, 32
+//   576 threads: 3D n = 24
 //   512 threads: 2D n = 64 and 3D n = 32
 #include "cells_2d.h"
 #include "cells_3d.h"
@@ -18,9 +19,36 @@ namespace qdvm {
 
 namespace {
 
-// LDS floats of the transpose buffers: 18 2D n=32 cells (576 threads) or one 3D
-// n=32 cell (512 threads); every other class of the family fits inside.
-__host__ __device__ constexpr int batched_xb_floats(int T) { return T == 576 ? 18 * 32 * 33 : 32 * 32 * 33; }
+// Values that are the same in every lane but were read from global memory (the
+// compiler cannot prove that): readfirstlane moves them to scalar registers, so
+// that buffer descriptors built from them need no per-lane loop.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uni(T* p) { return (T*)(size_t)uni((int64_t)(size_t)p); }
+
+__device__ __forceinline__ DevPlan uniform_plan(const DevPlan& p)
+{
+    DevPlan u;
+    u.dim = uni(p.dim); u.n = uni(p.n); u.ntilde = uni(p.ntilde); u.P = uni(p.P); u.njobs = uni(p.njobs);
+    u.npts = uni(p.npts); u.mode = uni(p.mode);
+    u.jobs = uni(p.jobs); u.dirichlet = uni(p.dirichlet); u.aperp = uni(p.aperp); u.w_default = uni(p.w_default);
+    u.dir_job = uni(p.dir_job); u.lam0 = uni(p.lam0); u.jobw0 = uni(p.jobw0);
+    return u;
+}
+
+// LDS floats of the transpose buffers: eight 2D n=32 cells (256 threads), one
+// 3D n=24 cell (576) or one 3D n=32 cell (512); every other class of a family
+// fits inside.
+__host__ __device__ constexpr int batched_xb_floats(int T)
+{
+    return T == 256 ? 8 * 32 * 33 : (T == 576 ? 24 * 24 * 25 : 32 * 32 * 33);
+}
 constexpr int kRedFloats = 160;   // 16 waves x 5 doubles
 
 template <int N, int T, bool SPLIT>
@@ -40,8 +68,8 @@ __device__ __forceinline__ void batch_item_2d(const DevPlan& pl, const BatchItem
     it.vcell = (int)((off + j) * 4);
     it.vspec = (local * NPTS + j) * 8;
     const rsrc_t rlam = make_rsrc(pl.lam0, NPTS * 4);
-    // registers of 576 / 512 threads hold the two transforms of a job up to n = 16
-    constexpr bool STAGE = N >= 32;
+    // at 512 threads the registers cannot hold two transforms of a 2D n = 64 job
+    constexpr bool STAGE = T == 512;
     if (SPLIT && pl.mode)
         cell2d_eval_split<N, 0, STAGE>(pl, it, make_rsrc(slot + b.gslot, (T / N) * NPTS * 8),
                                        make_rsrc(slot + 2 * b.gslot, (T / N) * NPTS * 8), rlam, pl.jobw0, dt,
@@ -56,7 +84,7 @@ __device__ __forceinline__ void batch_item_3d(const DevPlan& pl, const BatchItem
                                               const float* dtab, float2* slot, double* red)
 {
     constexpr int NPTS = N * N * N;
-    const int64_t off = b.cell_off[I.first];
+    const int64_t off = uni(b.cell_off[I.first]);
     Cell3D cl;
     cl.f = make_rsrc(f + off, NPTS * 4);
     cl.q = make_rsrc(q + off, NPTS * 4);
@@ -73,87 +101,130 @@ __device__ __forceinline__ void batch_item_3d(const DevPlan& pl, const BatchItem
 
 }  // namespace
 
-// SPLIT: the batch holds near-equilibrium plans (a separate instantiation, so
-// that the register allocation of plain batches is not affected).
-template <int T, int MINB, bool SPLIT>
-__global__ __launch_bounds__(T, MINB) void k_batched(BatchDev b, const float* f, float* q, float dt)
+// Drain the queue of one class.  Ticket k of a class is item k; the first
+// round is static (workgroup g takes ticket g), later tickets come from the
+// class's counter, which thread 0 bumps while the current item is being
+// computed, so the atomic's latency is hidden.  Each class runs its own loop,
+// so that its registers are allocated for its own cell code only.
+template <int C, int T, bool SPLIT>
+__device__ __forceinline__ void drain_class(const BatchDev& b, const float* f, float* q, float dt, float* dtab,
+                                            float* xbase, double* red, int* s_ticket, float2* slot, int& cur_plan)
 {
-    extern __shared__ float smem[];
-    __shared__ int s_item;
-    float* dtab = smem;
-    float* xbase = smem + b.dtab_floats;
-    double* red = (double*)(xbase + batched_xb_floats(T));   // block reductions of the near-equilibrium mode
-    float2* slot = b.spec + (size_t)blockIdx.x * b.slot_elems;
     const int tid = threadIdx.x;
-    int cur_plan = -1;
-    for (;;) {
-        __syncthreads();                      // the previous item no longer reads LDS or s_item
-        if (tid == 0) s_item = atomicAdd(b.counter, 1);
-        __syncthreads();
-        const int it = s_item;
-        if (it >= b.nitems) break;            // uniform: every thread read the same ticket
-        const BatchItem I = b.items[it];
-        const DevPlan pl = b.plans[I.plan];
+    __syncthreads();                          // the previous class's last ticket has been read
+    int t = blockIdx.x;
+    for (int k = 0;; ++k) {
+        // t is uniform; readfirstlane makes that visible, so the item, its plan
+        // and every buffer descriptor derived from them live in scalar registers
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= b.cls_count[C]) break;
+        if (tid == 0) s_ticket[k & 1] = (int)gridDim.x + atomicAdd(b.counter + C, 1);
+        const BatchItem Iv = b.items[b.cls_first[C] + t];
+        const BatchItem I = {uni(Iv.cls), uni(Iv.plan), uni(Iv.first), uni(Iv.count)};
+        const DevPlan pl = uniform_plan(b.plans[I.plan]);
         if (I.plan != cur_plan) {
-            for (int i = tid; i < (pl.ntilde + 1) * pl.n; i += T) dtab[i] = pl.dirichlet[i];
+            __syncthreads();                  // the previous item no longer reads the table
+            load_dtab(dtab, pl, tid, T);
             __syncthreads();
             cur_plan = I.plan;
         }
-        if constexpr (T == 576) {
-            switch (I.cls) {
-                case BC_2D8: batch_item_2d<8, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot); break;
-                case BC_2D16: batch_item_2d<16, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot); break;
-                case BC_2D32: batch_item_2d<32, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot); break;
-                case BC_3D24: batch_item_3d<24, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot, red); break;
-                default: break;
-            }
-        } else {
-            switch (I.cls) {
-                case BC_2D64: batch_item_2d<64, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot); break;
-                case BC_3D32: batch_item_3d<32, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot, red); break;
-                default: break;
-            }
-        }
+        if constexpr (C == BC_2D8) batch_item_2d<8, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot);
+        else if constexpr (C == BC_2D16) batch_item_2d<16, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot);
+        else if constexpr (C == BC_2D32) batch_item_2d<32, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot);
+        else if constexpr (C == BC_2D64) batch_item_2d<64, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot);
+        else if constexpr (C == BC_3D24) batch_item_3d<24, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot, red);
+        else batch_item_3d<32, T, SPLIT>(pl, I, b, f, q, dt, xbase, dtab, slot, red);
+        // the next ticket is visible, and the item no longer uses LDS; the
+        // other slot of s_ticket is written only after the next barrier
+        __syncthreads();
+        t = s_ticket[k & 1];
+    }
+}
+
+// SPLIT: the batch holds near-equilibrium plans (a separate instantiation, so
+// that the register allocation of plain batches is not affected).  The classes
+// of a family are drained one after the other, the most expensive first; a
+// workgroup that finds one queue empty moves on to the next.
+template <int T, bool SPLIT>
+__global__ __launch_bounds__(T) void k_batched(BatchDev b, const float* f, float* q, float dt)
+{
+    // dynamic LDS only, so that the Dirichlet rows start at LDS address 0 and
+    // are aligned to 4n bytes: table | transpose buffers | reductions | tickets
+    extern __shared__ float smem[];
+    float* dtab = smem;
+    float* xbase = smem + b.dtab_floats;
+    double* red = (double*)(xbase + batched_xb_floats(T));   // block reductions of the near-equilibrium mode
+    int* s_ticket = (int*)(xbase + batched_xb_floats(T) + kRedFloats);   // two slots
+    float2* slot = b.spec + (size_t)blockIdx.x * b.slot_elems;
+    int cur_plan = -1;
+    if constexpr (T == 256) {
+        if (b.cls_count[BC_2D32]) drain_class<BC_2D32, T, SPLIT>(b, f, q, dt, dtab, xbase, red, s_ticket, slot, cur_plan);
+        if (b.cls_count[BC_2D16]) drain_class<BC_2D16, T, SPLIT>(b, f, q, dt, dtab, xbase, red, s_ticket, slot, cur_plan);
+        if (b.cls_count[BC_2D8]) drain_class<BC_2D8, T, SPLIT>(b, f, q, dt, dtab, xbase, red, s_ticket, slot, cur_plan);
+    } else if constexpr (T == 576) {
+        drain_class<BC_3D24, T, SPLIT>(b, f, q, dt, dtab, xbase, red, s_ticket, slot, cur_plan);
+    } else {
+        if (b.cls_count[BC_3D32]) drain_class<BC_3D32, T, SPLIT>(b, f, q, dt, dtab, xbase, red, s_ticket, slot, cur_plan);
+        if (b.cls_count[BC_2D64]) drain_class<BC_2D64, T, SPLIT>(b, f, q, dt, dtab, xbase, red, s_ticket, slot, cur_plan);
     }
 }
 
 // The queue counter is cleared by a kernel (not a memset) so that the pair of
 // launches can be captured in a graph and replayed.
-__global__ void k_reset_counter(int32_t* counter) { *counter = 0; }
-
-hipError_t batched_launch_info(int family, int nitems, bool split, LaunchInfo& li, size_t dtab_floats)
+__global__ void k_reset_counter(int32_t* counter)
 {
-    hipError_t e;
-    if (family == BF_576) {
-        li.block = 576;
-        li.lds = sizeof(float) * (dtab_floats + batched_xb_floats(576) + kRedFloats);
-        e = split ? occupancy_grid(k_batched<576, 2, true>, 576, li.lds, nitems, li.grid)
-                  : occupancy_grid(k_batched<576, 2, false>, 576, li.lds, nitems, li.grid);
-    } else {
-        li.block = 512;
-        li.lds = sizeof(float) * (dtab_floats + batched_xb_floats(512) + kRedFloats);
-        e = split ? occupancy_grid(k_batched<512, 1, true>, 512, li.lds, nitems, li.grid)
-                  : occupancy_grid(k_batched<512, 1, false>, 512, li.lds, nitems, li.grid);
-    }
+    if (threadIdx.x < kNumClasses) counter[threadIdx.x] = 0;
+}
+
+namespace {
+
+template <int T>
+hipError_t family_info(int nitems, bool split, LaunchInfo& li, size_t dtab_floats)
+{
+    li.block = T;
+    li.lds = sizeof(float) * (dtab_floats + batched_xb_floats(T) + kRedFloats + 4);
+    hipError_t e = split ? occupancy_grid(k_batched<T, true>, T, li.lds, nitems, li.grid)
+                         : occupancy_grid(k_batched<T, false>, T, li.lds, nitems, li.grid);
     li.slots = li.grid;
     return e;
 }
 
-size_t batched_slot_elems(int family) { return family == BF_576 ? (size_t)18 * 32 * 32 : (size_t)32 * 32 * 32; }
+template <int T>
+void family_launch(const BatchDev& b, const LaunchInfo& li, const float* f, float* q, float dt, hipStream_t st)
+{
+    if (b.gslot != 0) hipLaunchKernelGGL((k_batched<T, true>), dim3(li.grid), dim3(T), li.lds, st, b, f, q, dt);
+    else hipLaunchKernelGGL((k_batched<T, false>), dim3(li.grid), dim3(T), li.lds, st, b, f, q, dt);
+}
+
+}  // namespace
+
+hipError_t batched_launch_info(int family, int nitems, bool split, LaunchInfo& li, size_t dtab_floats)
+{
+    switch (family) {
+        case BF_256: return family_info<256>(nitems, split, li, dtab_floats);
+        case BF_576: return family_info<576>(nitems, split, li, dtab_floats);
+        case BF_512: return family_info<512>(nitems, split, li, dtab_floats);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t batched_slot_elems(int family)
+{
+    // spectra of one work item: eight 2D n=32 cells, one 3D n=24 cell, one 3D n=32 cell / eight 2D n=64 cells
+    return family == BF_256 ? (size_t)8 * 32 * 32 : (family == BF_576 ? (size_t)24 * 24 * 24 : (size_t)32 * 32 * 32);
+}
 
 hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, const float* f, float* q, float dt,
                           hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, b.counter);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, b.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const bool split = b.gslot != 0;
-    if (family == BF_576) {
-        if (split) hipLaunchKernelGGL((k_batched<576, 2, true>), dim3(li.grid), dim3(576), li.lds, st, b, f, q, dt);
-        else hipLaunchKernelGGL((k_batched<576, 2, false>), dim3(li.grid), dim3(576), li.lds, st, b, f, q, dt);
-    } else {
-        if (split) hipLaunchKernelGGL((k_batched<512, 1, true>), dim3(li.grid), dim3(512), li.lds, st, b, f, q, dt);
-        else hipLaunchKernelGGL((k_batched<512, 1, false>), dim3(li.grid), dim3(512), li.lds, st, b, f, q, dt);
+    switch (family) {
+        case BF_256: family_launch<256>(b, li, f, q, dt, st); break;
+        case BF_576: family_launch<576>(b, li, f, q, dt, st); break;
+        case BF_512: family_launch<512>(b, li, f, q, dt, st); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

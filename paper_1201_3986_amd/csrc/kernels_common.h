@@ -61,6 +61,57 @@ __device__ __forceinline__ void bstore2(float2 x, rsrc_t r, int voff, int soff)
     __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
 }
 
+// Dirichlet table in LDS: the rows D_M(s) (M = 0..Nt, s = 0..n-1; alpha' in 2D)
+// followed by the rows D_M(s) - 1 (alpha), so that neither multiplier costs an
+// instruction per element.
+__device__ __forceinline__ int dtab_floats(const DevPlan& pl) { return 2 * (pl.ntilde + 1) * pl.n; }
+__device__ __forceinline__ void load_dtab(float* dtab, const DevPlan& pl, int tid, int nthreads)
+{
+    const int m = (pl.ntilde + 1) * pl.n;
+    for (int i = tid; i < m; i += nthreads) {
+        const float d = pl.dirichlet[i];
+        dtab[i] = d;
+        dtab[m + i] = d - 1.f;
+    }
+}
+__device__ __forceinline__ const float* dtab_alpha(const float* dtab, const DevPlan& pl)
+{
+    return dtab + (pl.ntilde + 1) * pl.n;
+}
+
+typedef __attribute__((address_space(3))) const float* lds_fptr;
+
+// LDS byte address of a pointer into shared memory.
+__device__ __forceinline__ uint32_t lds_byte_addr(const float* p) { return (uint32_t)(size_t)(lds_fptr)p; }
+
+// Walk along one row of n floats in LDS, the index moving by a fixed step per
+// element, modulo n.  When n is a power of two and the row starts at an LDS
+// address that is a multiple of 4n bytes, the offset is carried in bytes
+// without wrapping and the wrap plus the row address are one and-or per read.
+template <int N>
+struct RowWalk {
+    static constexpr bool kPow2 = (N & (N - 1)) == 0;
+    uint32_t row, off, step;
+    __device__ __forceinline__ RowWalk(const float* rowp, int start, int stride)   // 0 <= start, stride < n
+        : row(lds_byte_addr(rowp)), off(kPow2 ? 4u * start : (uint32_t)start),
+          step(kPow2 ? 4u * stride : (uint32_t)stride) {}
+    __device__ __forceinline__ float get() const
+    {
+        if constexpr (kPow2) {
+            // row | (off & m) as one bitfield insert (row has no bits below 4n)
+            uint32_t a;
+            asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(a) : "s"(4u * N - 1), "v"(off), "v"(row));
+            return *(lds_fptr)(size_t)a;
+        }
+        else return *(lds_fptr)(size_t)(row + 4u * off);
+    }
+    __device__ __forceinline__ void next()
+    {
+        off += step;
+        if constexpr (!kPow2) off -= (off >= (uint32_t)N) ? (uint32_t)N : 0u;
+    }
+};
+
 // The value unchanged, but opaque to the optimiser (no instruction is emitted):
 // stops it from reusing an expensive expression across a long stretch of code
 // where keeping the result alive would cost registers.

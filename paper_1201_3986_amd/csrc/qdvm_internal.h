@@ -115,25 +115,29 @@ hipError_t launch_vjp2d(const DevPlan& pl, int batch, const float* f, const floa
                         DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
 
 // ------------------------------------------------------------- heterogeneous batch
-enum BatchClass : int32_t { BC_2D8 = 0, BC_2D16 = 1, BC_2D32 = 2, BC_2D64 = 3, BC_3D24 = 4, BC_3D32 = 5 };
-enum BatchFamily : int32_t { BF_576 = 0, BF_512 = 1 };
+enum BatchClass : int32_t { BC_2D8 = 0, BC_2D16 = 1, BC_2D32 = 2, BC_2D64 = 3, BC_3D24 = 4, BC_3D32 = 5,
+                            kNumClasses = 6 };
+// block-size families of the batched launch: 256 threads (2D n = 8, 16, 32),
+// 576 (3D n = 24), 512 (2D n = 64, 3D n = 32)
+enum BatchFamily : int32_t { BF_256 = 0, BF_576 = 1, BF_512 = 2, kNumFamilies = 3 };
 
 struct BatchItem {
     int32_t cls, plan, first, count;   // class, plan slot, first entry in cell_off, cells
 };
 
 struct BatchDev {
-    const BatchItem* items;
+    const BatchItem* items;    // grouped by class, each group ordered by decreasing cost
     int32_t nitems;
+    int32_t cls_first[kNumClasses], cls_count[kNumClasses];   // item range of each class
     const DevPlan* plans;
     const int64_t* cell_off;   // element offset of each cell, in item order
-    int32_t* counter;
+    int32_t* counter;          // [kNumClasses] work-queue tickets, one queue per class
     float2* spec;              // [grid][slot_elems]
     int64_t slot_elems;
     int64_t gslot;             // near-equilibrium plans: the spectrum of g at slot + gslot and a staging
                                // area at slot + 2 gslot (slot_elems = 3 gslot); else 0
     uint32_t fbytes;           // extent of f and q in bytes
-    int32_t dtab_floats;       // LDS floats reserved for the Dirichlet table
+    int32_t dtab_floats;       // LDS floats reserved for the Dirichlet tables (D and D - 1 rows)
 };
 
 // dtab_floats must be even (the reduction area after the LDS buffers holds doubles)

@@ -65,17 +65,17 @@ def test_mixed_batch_equals_single_cell_and_oracle(gpu_lib):
     p24 = gpu_lib.Plan(3, 24, 8.0, num_dirs=16)
     rng = np.random.default_rng(4)
     cells = []
-    for i in range(45):           # 2D n=32: 2.5 items of 18 cells, two plans interleaved
+    for i in range(45):           # 2D n=32: items of 8 cells and ragged tails, two plans interleaved
         cells.append((p32 if i % 3 else p32b, workloads.random_positive(500 + i, 2, 32)[0]))
     for i in range(3):
         cells.append((p24, workloads.random_positive(600 + i, 3, 24)[0]))
-    for i in range(40):           # 2D n=16: 36 cells per item
+    for i in range(40):           # 2D n=16: 16 cells per item
         cells.append((p16, workloads.random_positive(700 + i, 2, 16)[0]))
     order = rng.permutation(len(cells))
     cells = [cells[k] for k in order]
     flat, offs = _layout(cells)
     b = gpu_lib.BatchPlan([c[0] for c in cells], offs)
-    assert b.launches == 1
+    assert b.launches == 2        # 256-thread family (2D) and 576-thread family (3D n=24)
     fd = _dev(flat)
     qd = b.eval(fd)
     torch.cuda.synchronize()
@@ -142,7 +142,7 @@ def test_config4_graph_step(gpu_lib):
     offs = np.concatenate([np.arange(len(f2)) * 1024, len(f2) * 1024 + np.arange(len(f3)) * 13824]).astype(np.int64)
     flat = np.concatenate([f2.reshape(-1), f3.reshape(-1)]).astype(np.float32)
     b = gpu_lib.BatchPlan(plans, offs)
-    assert b.launches == 1
+    assert b.launches == 2
     dt = wl["dt"]
     # eager reference trajectory
     ref = _dev(flat)
@@ -245,7 +245,7 @@ def test_config4_graph_step_near_equilibrium(gpu_lib):
     print("config4 near-eq: sampled rel errors vs definition: %s" % " ".join("%.2e" % e for e in errs_def))
     assert max(errs) <= TOL
     assert max(errs_def) <= TOL
-    # mixed batch: plain and near-equilibrium plans of both families together
+    # mixed batch: plain and near-equilibrium plans of every family together
     pf2 = gpu_lib.Plan(2, 32, 8.0, num_dirs=16)
     p64 = gpu_lib.Plan(2, 64, 8.0, num_dirs=8, mode=near)
     rng = np.random.default_rng(5)
