@@ -231,6 +231,20 @@ def main():
                                          "tflops": algorithmic_flops(2, 64, pl.num_jobs) * B / (t * 1e-3) / 1e12}
             pl.close()
         results["2d_n64_P16"] = {"cells_per_s": value, "ms": ms, "rel_err": err, "tflops": achieved}
+        # PCIe-inclusive rate: f from pinned host memory, Q back to pinned host memory
+        fh = torch.empty(f.shape, dtype=torch.float32, pin_memory=True)
+        fh.copy_(torch.from_numpy(f_np))
+        qh = torch.empty_like(fh, pin_memory=True)
+
+        def with_pcie():
+            f.copy_(fh, non_blocking=True)
+            plan.eval(f, out=q)
+            qh.copy_(q, non_blocking=True)
+        t = time_calls(with_pcie, max(5, args.steps // 4), 2)
+        results["2d_n64_P16_pcie_inclusive"] = {"cells_per_s": B / (t * 1e-3), "ms": t,
+                                                "note": "host f -> device, eval, Q -> host, one stream"}
+        log("PCIe-inclusive 2D n=64 P=16: %.3f ms (%.3e cells/s)" % (t, B / (t * 1e-3)))
+        del fh, qh
         # the same cells in the near-equilibrium mode (rel err against the oracle's Q(f, f))
         pn = qdvm.Plan(2, 64, 8.0, num_dirs=16, mode="near_equilibrium")
         t = time_calls(lambda: pn.eval(f, out=q), max(5, args.steps // 4), 2)

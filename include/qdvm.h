@@ -87,7 +87,7 @@ typedef struct {
  *     g = f - M, and the result is Q(f, f) - Q(M, M) = Q(g, f) + Q(M, g),
  *     evaluated with no transform mixing f-sized and g-sized data, so the error
  *     scales with |f| |g|.  Q(M, M) vanishes for an unwrapped discrete
- *     Maxwellian (every pair of the discrete sum of Sec. 2.2 cancels); what is left
+ *     Maxwellian (every pair of the discrete sum of Sec. 2.3 cancels); what is left
  *     out is its periodic-wrap residue.  About twice the transforms of
  *     QDVM_MODE_FULL.  A cell whose moments do not define a Maxwellian (mass
  *     <= 0, or index-space temperature <= 1/4) takes M = 0, i.e. Q(f, f).

@@ -191,7 +191,7 @@ __device__ __forceinline__ double group_sumd(double v)
 //     gain_j = line_j(g) plane_j(f) + (line_j(f) - line_j(g)) plane_j(g)
 //     loss   = g l(f) + M l(g).
 // Q(M, M) vanishes except for aliasing (every bracket of an unwrapped discrete
-// Maxwellian cancels, Sec. 2.2), and is left out: the result is
+// Maxwellian cancels in the pair sum of Sec. 2.3), and is left out: the result is
 // Q(f, f) - Q(M, M).  Errors scale with |f| |g| instead of |f|^2.
 // M is recomputed from its parameters where needed (FP64 exp) instead of being
 // kept in registers.  With STAGE the transform of g of each job is parked in
