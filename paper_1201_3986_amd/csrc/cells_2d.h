@@ -147,8 +147,11 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
     }
     inv2d<N, RV>(z, xb, j);
     float acc[N];
+    {
+        const int vc = reread(it.vcell);
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc[i] = -bload(it.f, it.vcell, i * RS) * z[i].x;
+        for (int i = 0; i < N; ++i) acc[i] = -bload(it.f, vc, i * RS) * z[i].x;
+    }
 
     // direction loop: g + i h = IFFT((alpha + i alpha') fhat), acc += W g h
     const float* atab = dtab_alpha(dtab, pl);
@@ -166,9 +169,9 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
 #pragma unroll
         for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
     } else {
+        const int vc = reread(it.vcell);
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            bstore(__builtin_fmaf(dt, acc[i], bload(it.f, it.vcell, i * RS)), it.q, it.vcell, i * RS);
+        for (int i = 0; i < N; ++i) bstore(__builtin_fmaf(dt, acc[i], bload(it.f, vc, i * RS)), it.q, it.vcell, i * RS);
     }
 }
 
@@ -232,8 +235,10 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
 
     float2 z[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+    for (int i = 0; i < N; ++i) {
         z[i] = make_float2((float)((double)bload(it.f, it.vcell, i * RS) - QDVM_MAXW(i)), 0.f);
+        QDVM_CHUNK_FENCE(i);
+    }
     fwd2d<N, RV>(z, xb, j);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -247,8 +252,11 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
     float acc[N];                                // holds l(g) until l(f) is formed
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[i] = z[i].x;
+    {
+        const int vc = reread(it.vcell);
 #pragma unroll
-    for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
+        for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, vc, i * RS), 0.f);
+    }
     fwd2d<N, RV>(z, xb, j);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -261,12 +269,14 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
     inv2d<N, RV>(z, xb, j);                      // l(f)
     {
         // M again (kept opaque so it is not carried over from the first evaluation)
-        const double iv = opaque(inv2v);
+        const double iv = opaque(inv2v), m0 = opaque(mu0);
+        const int vc = reread(it.vcell);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const double m = ej * exp(-((i) - mu0) * ((i) - mu0) * iv);
-            const float g = (float)((double)bload(it.f, it.vcell, i * RS) - m);
+            const double m = ej * exp(-((i) - m0) * ((i) - m0) * iv);
+            const float g = (float)((double)bload(it.f, vc, i * RS) - m);
             acc[i] = -__builtin_fmaf(g, z[i].x, (float)m * acc[i]);
+            QDVM_CHUNK_FENCE(i);
         }
     }
 #undef QDVM_MAXW
@@ -297,9 +307,9 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
 #pragma unroll
         for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
     } else {
+        const int vc = reread(it.vcell);
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            bstore(__builtin_fmaf(dt, acc[i], bload(it.f, it.vcell, i * RS)), it.q, it.vcell, i * RS);
+        for (int i = 0; i < N; ++i) bstore(__builtin_fmaf(dt, acc[i], bload(it.f, vc, i * RS)), it.q, it.vcell, i * RS);
     }
 }
 
@@ -331,51 +341,64 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
         QDVM_CHUNK_FENCE(k);
     }
     inv2d<N, RV>(z, xb, j);
-    float acc[N];
+    // -c l - C(cf) goes to grad_f now and is completed after the direction
+    // loop, so that no pencil-sized accumulator stays live through it
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc[i] = -bload(rc, it.vcell, i * RS) * z[i].x - z[i].y;
+    for (int i = 0; i < N; ++i) bstore(-bload(rc, it.vcell, i * RS) * z[i].x - z[i].y, it.q, it.vcell, i * RS);
 
+    const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = pl.jobs[jb];
         const float cw = jobw[jb];
         float spart = 0.f;
-        Mult2D m = mult2d_init<N>(J, dtab, j);
+        {
+            RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * j), modc<N>(J.e[1]));
+            RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const float2 F = bload2(it.fh, it.vspec, k * RS2);
-            const float2 C = bload2(rch, it.vspec, k * RS2);
-            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
-            z[k] = make_float2(al * F.x - ap * F.y, al * F.y + ap * F.x);
-            spart = __builtin_fmaf(al * ap, C.x * F.x + C.y * F.y, spart);
-            mult2d_step<N>(m);
-            QDVM_CHUNK_FENCE(k);
+            for (int k = 0; k < N; ++k) {
+                const float2 F = bload2(it.fh, it.vspec, k * RS2);
+                const float2 C = bload2(rch, it.vspec, k * RS2);
+                const float al = a.get(), ap = b.get();
+                z[k] = make_float2(__builtin_fmaf(al, F.x, -ap * F.y), __builtin_fmaf(al, F.y, ap * F.x));
+                spart = __builtin_fmaf(al * ap, __builtin_fmaf(C.x, F.x, C.y * F.y), spart);
+                a.next();
+                b.next();
+                QDVM_CHUNK_FENCE(k);
+            }
         }
         inv2d<N, RV>(z, xb, j);   // z = u + i v = n^2 (g + i h)
         float rpart = 0.f;
+        {
+            const int vc = reread(it.vcell);
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const float c = bload(rc, it.vcell, i * RS);
-            rpart = __builtin_fmaf(c * z[i].x, z[i].y, rpart);
-            z[i] = make_float2(c * z[i].y, c * z[i].x);   // c v + i c u
-            QDVM_CHUNK_FENCE(i);
+            for (int i = 0; i < N; ++i) {
+                const float c = bload(rc, vc, i * RS);
+                rpart = __builtin_fmaf(c * z[i].x, z[i].y, rpart);
+                z[i] = make_float2(c * z[i].y, c * z[i].x);   // c v + i c u
+                QDVM_CHUNK_FENCE(i);
+            }
         }
         const float tot = group_sum<N>(rpart * inv_n2 - spart * inv_n);
         if (j == 0 && valid) gwp[jb] = tot;
         fwd2d<N, RV>(z, xb, j);
-        m = mult2d_init<N>(J, dtab, j);
+        {
+            RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * j), modc<N>(J.e[1]));
+            RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const float al = m.D[m.s] - 1.f, ap = m.D[m.t];
-            // S += W (alpha - i alpha') Y
-            float2 t = make_float2(cw * (al * z[k].x + ap * z[k].y), cw * (al * z[k].y - ap * z[k].x));
-            if (jb > 0) {
-                const float2 sv = bload2(rsh, it.vspec, k * RS2);
-                t.x += sv.x;
-                t.y += sv.y;
+            for (int k = 0; k < N; ++k) {
+                const float al = cw * a.get(), ap = cw * b.get();
+                // S += W (alpha - i alpha') Y
+                float2 t = make_float2(__builtin_fmaf(al, z[k].x, ap * z[k].y), __builtin_fmaf(al, z[k].y, -ap * z[k].x));
+                if (jb > 0) {
+                    const float2 sv = bload2(rsh, it.vspec, k * RS2);
+                    t.x += sv.x;
+                    t.y += sv.y;
+                }
+                bstore2(t, rsh, it.vspec, k * RS2);
+                a.next();
+                b.next();
+                QDVM_CHUNK_FENCE(k);
             }
-            bstore2(t, rsh, it.vspec, k * RS2);
-            mult2d_step<N>(m);
-            QDVM_CHUNK_FENCE(k);
         }
     }
     if (pl.njobs > 0) {
@@ -383,10 +406,8 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
         for (int k = 0; k < N; ++k) z[k] = bload2(rsh, it.vspec, k * RS2);
         inv2d<N, RV>(z, xb, j);
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc[i] += z[i].x;
+        for (int i = 0; i < N; ++i) bstore(bload(it.q, it.vcell, i * RS) + z[i].x, it.q, it.vcell, i * RS);
     }
-#pragma unroll
-    for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
 }
 
 }  // namespace qdvm

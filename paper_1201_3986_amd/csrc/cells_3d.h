@@ -224,9 +224,8 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
     const double inv2v = ok ? 0.5 / var : 0.0;
     const double C = ok ? s0 / ((2.0 * kPi * var) * sqrt(2.0 * kPi * var)) : 0.0;
     // M(x, y, z) = eyz(y, z) ex(x): the n factors ex(x) sit in LDS after the
-    // reduction slots (block_sum5d uses at most 45 doubles)
-    static_assert(T <= 576, "reduction slots overlap the Maxwellian factors");
-    double* ex = red + 48;
+    // reduction slots of block_sum5d (5 doubles per wave)
+    double* ex = red + 5 * ((T + 63) / 64);
     if (tid < N) ex[tid] = ok ? exp(-(tid - mx) * (tid - mx) * inv2v) : 0.0;
     double eyz[Q];
 #pragma unroll
@@ -369,66 +368,69 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
             QDVM_CHUNK_FENCE(k);
         }
     inv3d<N, T, Q, RV>(z, xb, tid);
-    float acc[Q][N];
+    // -c l - C(cf) goes to grad_f now and is completed after the direction
+    // loop, so that no pencil-sized accumulator stays live through it
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int x = 0; x < N; ++x) acc[q][x] = -bload(rc, (tid + q * T) * 4, x * RS) * z[q][x].x - z[q][x].y;
+        for (int x = 0; x < N; ++x) {
+            const int v = (tid + q * T) * 4;
+            bstore(-bload(rc, v, x * RS) * z[q][x].x - z[q][x].y, cl.q, v, x * RS);
+        }
 
+    const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = pl.jobs[jb];
         const float cw = jobw[jb];
-        const float* D = dtab + J.M * N;
         const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
-        const int ds = modc<N>(J.e[2]);
         float spart = 0.f;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int pi = tid + q * T, kx = pi / N, ky = pi % N;
-            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+            RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const float2 F = bload2(cl.fh, pi * 8, k * RS2);
                 const float2 C = bload2(rch, pi * 8, k * RS2);
-                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
-                z[q][k] = make_float2(al * F.x - a2 * F.y, al * F.y + a2 * F.x);
-                spart = __builtin_fmaf(al * a2, C.x * F.x + C.y * F.y, spart);
-                sidx += ds;
-                sidx -= (sidx >= N) ? N : 0;
+                const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
+                z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
+                spart = __builtin_fmaf(al * a2, __builtin_fmaf(C.x, F.x, C.y * F.y), spart);
+                a.next();
                 QDVM_CHUNK_FENCE(k);
             }
         }
         inv3d<N, T, Q, RV>(z, xb, tid);
         float rpart = 0.f;
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
+        for (int q = 0; q < Q; ++q) {
+            const int v = reread((tid + q * T) * 4);
 #pragma unroll
             for (int x = 0; x < N; ++x) {
-                const float c = bload(rc, (tid + q * T) * 4, x * RS);
+                const float c = bload(rc, v, x * RS);
                 rpart = __builtin_fmaf(c * z[q][x].x, z[q][x].y, rpart);
                 z[q][x] = make_float2(c * z[q][x].y, c * z[q][x].x);
                 QDVM_CHUNK_FENCE(x);
             }
+        }
         const float tot = block_sum<N, T, Q>(rpart * inv_n2 - spart * inv_n, red, tid);
         if (tid == 0) gwp[jb] = tot;
         fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int pi = tid + q * T, kx = pi / N, ky = pi % N;
-            int sidx = modc<N>(J.e[0] * kx + J.e[1] * ky);
+            RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const float al = D[sidx] - 1.f, a2 = bload(rap, pi * 4, k * RS);
-                float2 t = make_float2(cw * (al * z[q][k].x + a2 * z[q][k].y),
-                                       cw * (al * z[q][k].y - a2 * z[q][k].x));
+                const float al = cw * a.get(), a2 = cw * bload(rap, pi * 4, k * RS);
+                float2 t = make_float2(__builtin_fmaf(al, z[q][k].x, a2 * z[q][k].y),
+                                       __builtin_fmaf(al, z[q][k].y, -a2 * z[q][k].x));
                 if (jb > 0) {
                     const float2 sv = bload2(rsh, pi * 8, k * RS2);
                     t.x += sv.x;
                     t.y += sv.y;
                 }
                 bstore2(t, rsh, pi * 8, k * RS2);
-                sidx += ds;
-                sidx -= (sidx >= N) ? N : 0;
+                a.next();
                 QDVM_CHUNK_FENCE(k);
             }
         }
@@ -442,12 +444,11 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int x = 0; x < N; ++x) acc[q][x] += z[q][x].x;
+            for (int x = 0; x < N; ++x) {
+                const int v = (tid + q * T) * 4;
+                bstore(bload(cl.q, v, x * RS) + z[q][x].x, cl.q, v, x * RS);
+            }
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int x = 0; x < N; ++x) bstore(acc[q][x], cl.q, (tid + q * T) * 4, x * RS);
 }
 
 }  // namespace qdvm

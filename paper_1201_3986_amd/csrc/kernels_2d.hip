@@ -48,16 +48,19 @@ __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const flo
     it.fh = make_rsrc(s.spec + (size_t)blockIdx.x * CPB * NPTS, CPB * NPTS * 8);
     it.vcell = (local * NPTS + j) * 4;
     it.vspec = (local * NPTS + j) * 8;
-    // near-equilibrium mode: the spectrum of g per slot (spec2 holds two slot sets; the second, a
-    // staging area, is not needed at 256 threads per block)
+    // near-equilibrium mode: the spectrum of g per slot (spec2 also holds a staging set, which
+    // these launches leave unused: at 256 threads both transforms of a job stay in registers)
+    constexpr bool STAGE = false;
     const rsrc_t rgh = make_rsrc(SPLIT ? s.spec2 + (size_t)blockIdx.x * CPB * NPTS : s.spec, CPB * NPTS * 8);
+    const rsrc_t rtg = make_rsrc(SPLIT ? s.spec2 + (size_t)(gridDim.x + blockIdx.x) * CPB * NPTS : s.spec,
+                                 CPB * NPTS * 8);
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int first = item * CPB;
         const int nvalid = min(CPB, batch - first);
         it.f = make_rsrc(f + (size_t)first * NPTS, nvalid * NPTS * 4);
         it.q = make_rsrc(q + (size_t)first * NPTS, nvalid * NPTS * 4);
         if constexpr (SPLIT)
-            cell2d_eval_split<N, RV, false>(pl, it, rgh, rgh, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
+            cell2d_eval_split<N, RV, STAGE>(pl, it, rgh, rtg, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
         else
             cell2d_eval<N, RV>(pl, it, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
     }

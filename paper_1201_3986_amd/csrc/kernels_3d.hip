@@ -44,7 +44,7 @@ __global__ __launch_bounds__(T) void k_eval3d(DevPlan pl, int batch, const float
     Cell3D cl;
     cl.fh = make_rsrc(s.spec + (size_t)blockIdx.x * NPTS, NPTS * 8);
     // near-equilibrium mode: spectrum of g, and for n = 32 (two transforms do not fit in the
-    // registers of 512 threads) a staging area for the transform of g of each job
+    // registers of 1024 threads) a staging area for the transform of g of each job
     constexpr bool STAGE = N == 32;
     const rsrc_t rgh = make_rsrc(SPLIT ? s.spec2 + (size_t)blockIdx.x * NPTS : s.spec, NPTS * 8);
     const rsrc_t rtg = make_rsrc(SPLIT ? s.spec2 + (size_t)(gridDim.x + blockIdx.x) * NPTS : s.spec, NPTS * 8);
@@ -166,11 +166,16 @@ namespace {
 template <int N>
 constexpr int t3d()
 {
-    return N == 32 ? 512 : (N == 24 ? 576 : (N == 16 ? 256 : 64));
+    return N == 32 ? 1024 : (N == 24 ? 576 : (N == 16 ? 256 : 64));
 }
 
+// transpose buffer | Dirichlet tables | reduction slots (5 doubles per wave) and n Maxwellian factors
 template <int N>
-size_t lds3d(int ntilde) { return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)2 * (ntilde + 1) * N + 160); }
+size_t lds3d(int ntilde)
+{
+    constexpr int T = t3d<N>();
+    return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)2 * (ntilde + 1) * N + 2 * (5 * ((T + 63) / 64) + N));
+}
 
 }  // namespace
 

@@ -49,7 +49,7 @@ __host__ __device__ constexpr int batched_xb_floats(int T)
 {
     return T == 256 ? 8 * 32 * 33 : (T == 576 ? 24 * 24 * 25 : 32 * 32 * 33);
 }
-constexpr int kRedFloats = 160;   // 16 waves x 5 doubles
+constexpr int kRedFloats = 2 * (5 * 9 + 32);   // 5 doubles per wave (up to 9 waves) and 32 Maxwellian factors
 
 template <int N, int T, bool SPLIT>
 __device__ __forceinline__ void batch_item_2d(const DevPlan& pl, const BatchItem& I, const BatchDev& b,

@@ -112,6 +112,15 @@ struct RowWalk {
     }
 };
 
+// A byte offset unchanged, but opaque to the optimiser: a later read of a cell
+// through it is not merged with an earlier read of the same address, which
+// would keep the whole pencil alive in registers in between.
+__device__ __forceinline__ int reread(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // The value unchanged, but opaque to the optimiser (no instruction is emitted):
 // stops it from reusing an expensive expression across a long stretch of code
 // where keeping the result alive would cost registers.
