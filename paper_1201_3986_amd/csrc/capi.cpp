@@ -117,12 +117,13 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout for one call: lam | jobw | spec | spec2 | acc | gw_part.
 struct WsLayout {
-    size_t lam, jobw, spec, spec2, acc, gw, total;
+    size_t lam, jobw, spec, spec2, acc, gw, part, total;
 };
 
-WsLayout ws_layout(const qdvm::HostPlan& hp, int slots, int batch, bool adjoint)
+WsLayout ws_layout(const qdvm::HostPlan& hp, const qdvm::LaunchInfo& li, int batch, bool adjoint)
 {
     WsLayout L{};
+    const int slots = li.slots;
     const size_t npts = (size_t)hp.npts();
     size_t off = 0;
     L.lam = off; off = align_up(off + sizeof(float) * npts);
@@ -135,6 +136,9 @@ WsLayout ws_layout(const qdvm::HostPlan& hp, int slots, int batch, bool adjoint)
     if (adjoint) {
         L.acc = off; off = align_up(off + sizeof(float2) * npts * slots);
         L.gw = off; off = align_up(off + sizeof(float) * std::max<size_t>(1, hp.jobs.size()) * batch);
+    }
+    if (li.jsplit > 1) {
+        L.part = off; off = align_up(off + sizeof(float) * npts * (size_t)batch * li.jsplit);
     }
     L.total = off;
     return L;
@@ -162,7 +166,7 @@ qdvm_status ensure_ws(qdvm::HostPlan& hp, size_t bytes, hipStream_t st)
     return QDVM_OK;
 }
 
-qdvm::DevScratch scratch_of(const qdvm::HostPlan& hp, const WsLayout& L, bool adjoint)
+qdvm::DevScratch scratch_of(const qdvm::HostPlan& hp, const WsLayout& L, bool adjoint, int jsplit)
 {
     char* b = (char*)hp.d_ws;
     qdvm::DevScratch s{};
@@ -174,6 +178,7 @@ qdvm::DevScratch scratch_of(const qdvm::HostPlan& hp, const WsLayout& L, bool ad
         s.acc = (float2*)(b + L.acc);
         s.gw_part = (float*)(b + L.gw);
     }
+    if (jsplit > 1) s.part = (float*)(b + L.part);
     return s;
 }
 
@@ -186,10 +191,10 @@ qdvm_status do_eval(qdvm_plan_s* p, int batch, const float* f, float* q, const f
     const qdvm::DevPlan pl = hp.dev();
     qdvm::LaunchInfo li = qdvm::eval_launch_info(pl, batch, variant);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
-    WsLayout L = ws_layout(hp, li.slots, batch, false);
+    WsLayout L = ws_layout(hp, li, batch, false);
     qdvm_status s = ensure_ws(hp, L.total, st);
     if (s != QDVM_OK) return s;
-    qdvm::DevScratch sc = scratch_of(hp, L, false);
+    qdvm::DevScratch sc = scratch_of(hp, L, false, li.jsplit);
     hipError_t e = hipSuccess;
     if (w) {
         e = qdvm::launch_prep(pl, w, sc, st);
@@ -211,10 +216,10 @@ qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, co
     const qdvm::DevPlan pl = hp.dev();
     qdvm::LaunchInfo li = qdvm::vjp_launch_info(pl, batch, variant);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the adjoint kernel");
-    WsLayout L = ws_layout(hp, li.slots, batch, true);
+    WsLayout L = ws_layout(hp, li, batch, true);
     qdvm_status s = ensure_ws(hp, L.total, st);
     if (s != QDVM_OK) return s;
-    qdvm::DevScratch sc = scratch_of(hp, L, true);
+    qdvm::DevScratch sc = scratch_of(hp, L, true, li.jsplit);
     hipError_t e = hipSuccess;
     if (w) {
         e = qdvm::launch_prep(pl, w, sc, st);

@@ -117,9 +117,12 @@ __device__ __forceinline__ void job3d_multiply(float2 (&z)[Q][N], rsrc_t rs, con
 }
 
 template <int N, int T, int RV>
+// Jobs jb0, jb0 + jstep, ... of the direction loop; the loss only if `loss`
+// (a cell whose jobs are spread over several workgroups: each writes its part).
 __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl, rsrc_t rlam,
                                             const float* __restrict__ jobw, float dt, float* xb,
-                                            const float* dtab, int tid)
+                                            const float* dtab, int tid, int jb0 = 0, int jstep = 1,
+                                            bool loss = true)
 {
     constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
     float2 z[Q][N];
@@ -128,25 +131,35 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 #pragma unroll
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
-            const float l = bload(rlam, (tid + q * T) * 4, k * RS);
-            z[q][k].x *= l;
-            z[q][k].y *= l;
-            QDVM_CHUNK_FENCE(k);
-        }
-    inv3d<N, T, Q, RV>(z, xb, tid);
     float acc[Q][N];
+    if (loss) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int x = 0; x < N; ++x) acc[q][x] = -bload(cl.f, (tid + q * T) * 4, x * RS) * z[q][x].x;
+            for (int k = 0; k < N; ++k) {
+                bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
+                const float l = bload(rlam, (tid + q * T) * 4, k * RS);
+                z[q][k].x *= l;
+                z[q][k].y *= l;
+                QDVM_CHUNK_FENCE(k);
+            }
+        inv3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) acc[q][x] = -bload(cl.f, (tid + q * T) * 4, x * RS) * z[q][x].x;
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
+                acc[q][k] = 0.f;
+            }
+    }
 
     const float* atab = dtab_alpha(dtab, pl);
-    for (int jb = 0; jb < pl.njobs; ++jb) {
+    for (int jb = jb0; jb < pl.njobs; jb += jstep) {
         const JobDesc J = pl.jobs[jb];
         const float cw = jobw[jb];
         job3d_multiply<N, T, Q>(z, cl.fh, pl, J, jb, atab, tid);
@@ -331,10 +344,12 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
 // which uses A(c h) + B(c g) = Re IFFT((a - i a') F(c h + i c g)), valid because
 // the multipliers a = alpha_j and a' = alpha'_j are real and even.
 template <int N, int T, int RV>
+// Jobs jb0, jb0 + jstep, ...; the loss part only if `loss` (see cell3d_eval).
 __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, rsrc_t rc, rsrc_t rch,
                                            rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
                                            float* __restrict__ gwp, float inv_n2, float inv_n, float* xb,
-                                           float* red, const float* dtab, int tid)
+                                           float* red, const float* dtab, int tid, int jb0 = 0, int jstep = 1,
+                                           bool loss = true)
 {
     constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
     float2 z[Q][N];
@@ -356,30 +371,41 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
             QDVM_CHUNK_FENCE(x);
         }
     fwd3d<N, T, Q, RV>(z, xb, tid);
+    if (loss) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const int pi = tid + q * T;
-            bstore2(z[q][k], rch, pi * 8, k * RS2);
-            const float2 F = bload2(cl.fh, pi * 8, k * RS2);
-            const float l = bload(rlam, pi * 4, k * RS);
-            z[q][k] = make_float2(l * (F.x - z[q][k].y), l * (F.y + z[q][k].x));
-            QDVM_CHUNK_FENCE(k);
-        }
-    inv3d<N, T, Q, RV>(z, xb, tid);
-    // -c l - C(cf) goes to grad_f now and is completed after the direction
-    // loop, so that no pencil-sized accumulator stays live through it
+            for (int k = 0; k < N; ++k) {
+                const int pi = tid + q * T;
+                bstore2(z[q][k], rch, pi * 8, k * RS2);
+                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+                const float l = bload(rlam, pi * 4, k * RS);
+                z[q][k] = make_float2(l * (F.x - z[q][k].y), l * (F.y + z[q][k].x));
+                QDVM_CHUNK_FENCE(k);
+            }
+        inv3d<N, T, Q, RV>(z, xb, tid);
+        // -c l - C(cf) goes to grad_f now and is completed after the direction
+        // loop, so that no pencil-sized accumulator stays live through it
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int x = 0; x < N; ++x) {
-            const int v = (tid + q * T) * 4;
-            bstore(-bload(rc, v, x * RS) * z[q][x].x - z[q][x].y, cl.q, v, x * RS);
-        }
+            for (int x = 0; x < N; ++x) {
+                const int v = (tid + q * T) * 4;
+                bstore(-bload(rc, v, x * RS) * z[q][x].x - z[q][x].y, cl.q, v, x * RS);
+            }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int pi = tid + q * T;
+                bstore2(z[q][k], rch, pi * 8, k * RS2);
+                bstore(0.f, cl.q, pi * 4, k * RS);
+            }
+    }
 
     const float* atab = dtab_alpha(dtab, pl);
-    for (int jb = 0; jb < pl.njobs; ++jb) {
+    for (int jb = jb0; jb < pl.njobs; jb += jstep) {
         const JobDesc J = pl.jobs[jb];
         const float cw = jobw[jb];
         const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
@@ -424,7 +450,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
                 const float al = cw * a.get(), a2 = cw * bload(rap, pi * 4, k * RS);
                 float2 t = make_float2(__builtin_fmaf(al, z[q][k].x, a2 * z[q][k].y),
                                        __builtin_fmaf(al, z[q][k].y, -a2 * z[q][k].x));
-                if (jb > 0) {
+                if (jb > jb0) {
                     const float2 sv = bload2(rsh, pi * 8, k * RS2);
                     t.x += sv.x;
                     t.y += sv.y;
@@ -435,7 +461,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
             }
         }
     }
-    if (pl.njobs > 0) {
+    if (jb0 < pl.njobs) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll

@@ -88,6 +88,66 @@ __global__ __launch_bounds__(T) void k_vjp3d(DevPlan pl, int batch, const float*
     }
 }
 
+// ------------------------------------------------------------------ direction-split launches
+// When a batch has fewer cells than the GPU has workgroup slots, the direction
+// loop of each cell is spread over G workgroups (workgroup b: cell b / G, jobs
+// b % G, b % G + G, ...).  Each computes the forward transform(s) itself, the
+// first of them also the loss, and writes its part of Q (or grad_f) to its
+// own buffer; k_combine adds the G parts in a fixed order.
+template <int N, int T, int RV>
+__global__ __launch_bounds__(T) void k_eval3d_js(DevPlan pl, int batch, int G, const float* f, DevScratch s)
+{
+    constexpr int NN = N * N, NPTS = NN * N;
+    extern __shared__ float smem[];
+    float* xb = smem;
+    float* dtab = smem + N * N * (N + 1);
+    const int tid = threadIdx.x;
+    load_dtab(dtab, pl, tid, T);
+    __syncthreads();
+    const int cell = blockIdx.x / G, g = blockIdx.x % G;
+    Cell3D cl;
+    cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
+    cl.q = make_rsrc(s.part + ((size_t)g * batch + cell) * NPTS, NPTS * 4);
+    cl.fh = make_rsrc(s.spec + (size_t)blockIdx.x * NPTS, NPTS * 8);
+    cell3d_eval<N, T, RV>(pl, cl, make_rsrc(s.lam, NPTS * 4), s.jobw, 0.f, xb, dtab, tid, g, G, g == 0);
+}
+
+template <int N, int T, int RV>
+__global__ __launch_bounds__(T) void k_vjp3d_js(DevPlan pl, int batch, int G, const float* __restrict__ f,
+                                                const float* __restrict__ c, DevScratch s)
+{
+    constexpr int NN = N * N, NPTS = NN * N;
+    extern __shared__ float smem[];
+    float* xb = smem;
+    float* dtab = smem + N * N * (N + 1);
+    float* red = dtab + dtab_floats(pl);
+    const int tid = threadIdx.x;
+    load_dtab(dtab, pl, tid, T);
+    __syncthreads();
+    const int cell = blockIdx.x / G, g = blockIdx.x % G;
+    const size_t slot = (size_t)blockIdx.x * NPTS;
+    const float inv_n = 1.f / (float)NPTS;
+    Cell3D cl;
+    cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
+    cl.q = make_rsrc(s.part + ((size_t)g * batch + cell) * NPTS, NPTS * 4);
+    cl.fh = make_rsrc(s.spec + slot, NPTS * 8);
+    cell3d_vjp<N, T, RV>(pl, cl, make_rsrc(c + (size_t)cell * NPTS, NPTS * 4), make_rsrc(s.spec2 + slot, NPTS * 8),
+                         make_rsrc(s.acc + slot, NPTS * 8), make_rsrc(s.lam, NPTS * 4), s.jobw,
+                         s.gw_part + (size_t)cell * pl.njobs, inv_n * inv_n, inv_n, xb, red, dtab, tid, g, G,
+                         g == 0);
+}
+
+// out = sum_g part[g] (g ascending), or f + dt * sum when dt != 0; out may equal f.
+__global__ void k_combine(int64_t total, int G, const float* __restrict__ part, const float* f, float* out, float dt)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        float acc = 0.f;
+        for (int g = 0; g < G; ++g) acc += part[(size_t)g * total + i];
+        out[i] = dt == 0.f ? acc : __builtin_fmaf(dt, acc, f[i]);
+    }
+}
+
 // ------------------------------------------------------------------ prep
 // Lambda/n^d at every spectral index and the job weights W_j / n^{2d}, from the
 // per-direction weights w (W_j = w_p + w_pp for a 2D perpendicular pair).
@@ -177,6 +237,18 @@ size_t lds3d(int ntilde)
     return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)2 * (ntilde + 1) * N + 2 * (5 * ((T + 63) / 64) + N));
 }
 
+// Spread each cell's direction loop over G workgroups when the batch leaves
+// more than half of the workgroup slots (cap) idle.
+void choose_split(const DevPlan& pl, int batch, int cap, LaunchInfo& li)
+{
+    if (batch < 1 || pl.njobs < 2 || 2 * batch > cap) return;
+    const int G = std::min(std::min(pl.njobs, 8), cap / batch);
+    if (G < 2) return;
+    li.jsplit = G;
+    li.grid = batch * G;
+    li.slots = li.grid;
+}
+
 }  // namespace
 
 #define QDVM_SWITCH_3D(N_, ...)                          \
@@ -215,6 +287,12 @@ LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant)
                     e = variant ? occupancy_grid(k_eval3d<N, T, 1, false>, T, li.lds, batch, li.grid)
                                 : occupancy_grid(k_eval3d<N, T, 0, false>, T, li.lds, batch, li.grid);
                 li.slots = li.grid;
+                if (e == hipSuccess && !pl.mode) {
+                    int cap = 0;
+                    e = variant ? occupancy_grid(k_eval3d_js<N, T, 1>, T, li.lds, 1 << 30, cap)
+                                : occupancy_grid(k_eval3d_js<N, T, 0>, T, li.lds, 1 << 30, cap);
+                    choose_split(pl, batch, cap, li);
+                }
             });
             return e;
         };
@@ -231,7 +309,13 @@ hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, f
     QDVM_SWITCH_3D(pl.n, {
         constexpr int T = t3d<N>();
         const dim3 g(li.grid), b(T);
-        if (pl.mode) {
+        if (li.jsplit > 1) {
+            if (variant) hipLaunchKernelGGL((k_eval3d_js<N, T, 1>), g, b, li.lds, st, pl, batch, li.jsplit, f, s);
+            else hipLaunchKernelGGL((k_eval3d_js<N, T, 0>), g, b, li.lds, st, pl, batch, li.jsplit, f, s);
+            const int64_t total = (int64_t)batch * pl.npts;
+            hipLaunchKernelGGL(k_combine, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)), dim3(256), 0,
+                               st, total, li.jsplit, s.part, f, q, dt);
+        } else if (pl.mode) {
             if (variant) hipLaunchKernelGGL((k_eval3d<N, T, 1, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
             else hipLaunchKernelGGL((k_eval3d<N, T, 0, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
         } else {
@@ -257,6 +341,12 @@ LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant)
                 e = variant ? occupancy_grid(k_vjp3d<N, T, 1>, T, li.lds, batch, li.grid)
                             : occupancy_grid(k_vjp3d<N, T, 0>, T, li.lds, batch, li.grid);
                 li.slots = li.grid;
+                if (e == hipSuccess) {
+                    int cap = 0;
+                    e = variant ? occupancy_grid(k_vjp3d_js<N, T, 1>, T, li.lds, 1 << 30, cap)
+                                : occupancy_grid(k_vjp3d_js<N, T, 0>, T, li.lds, 1 << 30, cap);
+                    choose_split(pl, batch, cap, li);
+                }
             });
             return e;
         };
@@ -278,7 +368,18 @@ hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float*
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
                 constexpr int T = t3d<N>();
-                if (variant)
+                if (li.jsplit > 1) {
+                    if (variant)
+                        hipLaunchKernelGGL((k_vjp3d_js<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch,
+                                           li.jsplit, f, c, s);
+                    else
+                        hipLaunchKernelGGL((k_vjp3d_js<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch,
+                                           li.jsplit, f, c, s);
+                    const int64_t total = (int64_t)batch * pl.npts;
+                    hipLaunchKernelGGL(k_combine, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)),
+                                       dim3(256), 0, st, total, li.jsplit, s.part, (const float*)nullptr, grad_f,
+                                       0.f);
+                } else if (variant)
                     hipLaunchKernelGGL((k_vjp3d<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, c,
                                        grad_f, s);
                 else

@@ -41,6 +41,7 @@ struct DevScratch {
     float2* spec2;   // [slots * npts] second spectral buffer (adjoint; g in near-equilibrium mode)
     float2* acc;     // [slots * npts] spectral accumulator (adjoint)
     float* gw_part;  // [batch * njobs] per-cell job partials of grad_w (adjoint)
+    float* part;     // [jsplit][batch][npts] per-workgroup parts of Q or grad_f (direction-split launches)
     int32_t* counter;  // work-queue counter (batched)
 };
 
@@ -94,7 +95,8 @@ bool supported_size(int dim, int n);
 struct LaunchInfo {
     int grid = 0, block = 0;
     size_t lds = 0;
-    int slots = 0;   // resident cell slots that need spectral scratch
+    int slots = 0;    // resident cell slots that need spectral scratch
+    int jsplit = 1;   // > 1: each cell's direction loop is spread over jsplit workgroups
 };
 
 hipError_t launch_prep(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st);

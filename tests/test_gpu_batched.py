@@ -45,6 +45,19 @@ def loss_total(plan, f):
     return float(np.sum(f * tot))
 
 
+def assert_same_cell(plan, got, single):
+    """The batched launch runs the single-cell device code, so 2D cells match the
+    single-plan result bit for bit.  A small 3D batch through the single-plan
+    path spreads each cell's directions over several workgroups and adds their
+    parts in another order, so 3D cells agree to rounding."""
+    got = np.asarray(got).reshape(-1)
+    single = np.asarray(single).reshape(-1)
+    if plan.dim == 2:
+        assert np.array_equal(got, single)
+    else:
+        assert rel_linf(got, single) <= 1e-6
+
+
 def _layout(cells):
     """cells: list of (plan, array) -> flat f, offsets (with gaps between cells)."""
     offs, pos = [], 0
@@ -83,7 +96,7 @@ def test_mixed_batch_equals_single_cell_and_oracle(gpu_lib):
     for k, ((plan, a), o) in enumerate(zip(cells, offs)):
         single = plan.eval(_dev(a))
         torch.cuda.synchronize()
-        assert np.array_equal(q[o:o + plan.npts], single.cpu().numpy().reshape(-1)), k
+        assert_same_cell(plan, q[o:o + plan.npts], single.cpu().numpy())
     for k in (0, 7, len(cells) - 1):
         plan, a = cells[k]
         o = offs[k]
@@ -110,7 +123,7 @@ def test_two_families_and_in_place_euler(gpu_lib):
     for (plan, a), o in zip(cells, offs):
         ref = plan.eval(_dev(a), dt=dt)
         torch.cuda.synchronize()
-        assert np.array_equal(got[o:o + plan.npts], ref.cpu().numpy().reshape(-1))
+        assert_same_cell(plan, got[o:o + plan.npts], ref.cpu().numpy())
     # gaps between cells untouched
     mask = np.ones(len(flat), bool)
     for (plan, a), o in zip(cells, offs):
@@ -259,4 +272,4 @@ def test_config4_graph_step_near_equilibrium(gpu_lib):
     for (plan, a), o in zip(cells, moffs):
         single = plan.eval(_dev(a.reshape(1, -1)))
         torch.cuda.synchronize()
-        assert np.array_equal(mq[o:o + plan.npts], single.cpu().numpy().reshape(-1))
+        assert_same_cell(plan, mq[o:o + plan.npts], single.cpu().numpy())
