@@ -584,11 +584,20 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
         std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& c) {
             return a.it.cls != c.it.cls ? a.it.cls < c.it.cls : a.cost > c.cost;
         });
-        for (int k = 0; k < qdvm::kNumClasses; ++k) F.dev.cls_first[k] = F.dev.cls_count[k] = 0;
+        for (int k = 0; k < qdvm::kNumClasses; ++k) {
+            F.dev.cls_first[k] = F.dev.cls_count[k] = 0;
+            F.dev.cls_static[k] = 1;
+        }
+        double first_cost[qdvm::kNumClasses] = {0, 0, 0, 0, 0, 0};
         for (auto& t : tmp) {
             t.it.first = (int32_t)F.cell_off.size();
             for (int32_t c : t.cells) F.cell_off.push_back(cell_offset[c]);
-            if (F.dev.cls_count[t.it.cls]++ == 0) F.dev.cls_first[t.it.cls] = (int32_t)F.items.size();
+            if (F.dev.cls_count[t.it.cls]++ == 0) {
+                F.dev.cls_first[t.it.cls] = (int32_t)F.items.size();
+                first_cost[t.it.cls] = t.cost;
+            } else if (t.cost != first_cost[t.it.cls]) {
+                F.dev.cls_static[t.it.cls] = 0;   // uneven items: dynamic queue
+            }
             F.items.push_back(t.it);
         }
         dtab_floats = (dtab_floats + 1) & ~size_t(1);

@@ -156,8 +156,8 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
     // direction loop: g + i h = IFFT((alpha + i alpha') fhat), acc += W g h
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
-        const JobDesc J = pl.jobs[jb];
-        const float cw = jobw[jb];
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(jobw, jb);
         job2d_multiply<N>(z, it.fh, it.vspec, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);
 #pragma unroll
@@ -283,8 +283,8 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
-        const JobDesc J = pl.jobs[jb];
-        const float cw = jobw[jb];
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(jobw, jb);
         float2 tg[N];
         job2d_multiply<N>(tg, rgh, it.vspec, J, dtab, atab, j);
         inv2d<N, RV>(tg, xb, j);                 // line(g) + i plane(g)
@@ -348,8 +348,8 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
-        const JobDesc J = pl.jobs[jb];
-        const float cw = jobw[jb];
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(jobw, jb);
         float spart = 0.f;
         {
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * j), modc<N>(J.e[1]));

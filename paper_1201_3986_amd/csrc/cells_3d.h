@@ -160,8 +160,8 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = jb0; jb < pl.njobs; jb += jstep) {
-        const JobDesc J = pl.jobs[jb];
-        const float cw = jobw[jb];
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(jobw, jb);
         job3d_multiply<N, T, Q>(z, cl.fh, pl, J, jb, atab, tid);
         inv3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
@@ -303,8 +303,8 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
-        const JobDesc J = pl.jobs[jb];
-        const float cw = jobw[jb];
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(jobw, jb);
         float2 tg[Q][N];
         job3d_multiply<N, T, Q>(tg, rgh, pl, J, jb, atab, tid);
         inv3d<N, T, Q, RV>(tg, xb, tid);         // line(g) + i plane(g)
@@ -406,8 +406,8 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = jb0; jb < pl.njobs; jb += jstep) {
-        const JobDesc J = pl.jobs[jb];
-        const float cw = jobw[jb];
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(jobw, jb);
         const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
         float spart = 0.f;
 #pragma unroll

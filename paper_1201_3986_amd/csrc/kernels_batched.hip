@@ -102,9 +102,10 @@ __device__ __forceinline__ void batch_item_3d(const DevPlan& pl, const BatchItem
 }  // namespace
 
 // Drain the queue of one class.  Ticket k of a class is item k; the first
-// round is static (workgroup g takes ticket g), later tickets come from the
+// round is static (workgroup g takes ticket g).  Later tickets come from the
 // class's counter, which thread 0 bumps while the current item is being
-// computed, so the atomic's latency is hidden.  Each class runs its own loop,
+// computed, so the atomic's latency is hidden -- or, when every item of the
+// class costs the same, statically (g, g + grid, ...), which measured faster.  Each class runs its own loop,
 // so that its registers are allocated for its own cell code only.
 template <int C, int T, bool SPLIT>
 __device__ __forceinline__ void drain_class(const BatchDev& b, const float* f, float* q, float dt, float* dtab,
@@ -118,7 +119,8 @@ __device__ __forceinline__ void drain_class(const BatchDev& b, const float* f, f
         // and every buffer descriptor derived from them live in scalar registers
         t = __builtin_amdgcn_readfirstlane(t);
         if (t >= b.cls_count[C]) break;
-        if (tid == 0) s_ticket[k & 1] = (int)gridDim.x + atomicAdd(b.counter + C, 1);
+        if (tid == 0)
+            s_ticket[k & 1] = b.cls_static[C] ? t + (int)gridDim.x : (int)gridDim.x + atomicAdd(b.counter + C, 1);
         const BatchItem Iv = b.items[b.cls_first[C] + t];
         const BatchItem I = {uni(Iv.cls), uni(Iv.plan), uni(Iv.first), uni(Iv.count)};
         const DevPlan pl = uniform_plan(b.plans[I.plan]);
@@ -183,6 +185,9 @@ hipError_t family_info(int nitems, bool split, LaunchInfo& li, size_t dtab_float
 {
     li.block = T;
     li.lds = sizeof(float) * (dtab_floats + batched_xb_floats(T) + kRedFloats + 4);
+    // 576 threads: one workgroup per CU (a second resident nine-wave workgroup
+    // measured slower: their barriers interleave on the SIMDs)
+    if (T == 576) li.lds = std::max<size_t>(li.lds, 81 * 1024);
     hipError_t e = split ? occupancy_grid(k_batched<T, true>, T, li.lds, nitems, li.grid)
                          : occupancy_grid(k_batched<T, false>, T, li.lds, nitems, li.grid);
     li.slots = li.grid;

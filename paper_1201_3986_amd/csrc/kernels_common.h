@@ -61,6 +61,22 @@ __device__ __forceinline__ void bstore2(float2 x, rsrc_t r, int voff, int soff)
     __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
 }
 
+// Plan data lives in global memory; reading it through a global-address-space
+// pointer keeps the compiler from using flat loads (which also count against
+// the LDS wait counter) when the plan was itself read from memory.
+template <class T>
+__device__ __forceinline__ T gload(const T* p, int i)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized plan records");
+    const __attribute__((address_space(1))) int* w = (const __attribute__((address_space(1))) int*)(p + i);
+    int words[sizeof(T) / 4];
+#pragma unroll
+    for (unsigned k = 0; k < sizeof(T) / 4; ++k) words[k] = w[k];
+    T v;
+    __builtin_memcpy(&v, words, sizeof(T));
+    return v;
+}
+
 // Dirichlet table in LDS: the rows D_M(s) (M = 0..Nt, s = 0..n-1; alpha' in 2D)
 // followed by the rows D_M(s) - 1 (alpha), so that neither multiplier costs an
 // instruction per element.
@@ -69,7 +85,7 @@ __device__ __forceinline__ void load_dtab(float* dtab, const DevPlan& pl, int ti
 {
     const int m = (pl.ntilde + 1) * pl.n;
     for (int i = tid; i < m; i += nthreads) {
-        const float d = pl.dirichlet[i];
+        const float d = gload(pl.dirichlet, i);
         dtab[i] = d;
         dtab[m + i] = d - 1.f;
     }

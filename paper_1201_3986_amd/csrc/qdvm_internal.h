@@ -131,6 +131,7 @@ struct BatchDev {
     const BatchItem* items;    // grouped by class, each group ordered by decreasing cost
     int32_t nitems;
     int32_t cls_first[kNumClasses], cls_count[kNumClasses];   // item range of each class
+    int32_t cls_static[kNumClasses];   // 1: the class's items cost the same, tickets are assigned statically
     const DevPlan* plans;
     const int64_t* cell_off;   // element offset of each cell, in item order
     int32_t* counter;          // [kNumClasses] work-queue tickets, one queue per class
