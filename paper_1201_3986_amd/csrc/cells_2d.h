@@ -100,6 +100,13 @@ struct Item2D {
     int vspec;           // byte offset of this lane's pencil in spectral arrays (float2)
 };
 
+// Half-stored spectrum of one 2D cell slot at the lane's row K0 = j (mirror row -j).
+template <int N>
+__device__ __forceinline__ HalfSpec<N, N * 8> half2d(rsrc_t r, int vspec, int j)
+{
+    return HalfSpec<N, N * 8>{r, vspec, vspec + ((((N - j) & (N - 1)) - j) * 8)};
+}
+
 // z = (alpha + i alpha') * spectrum for one job, the spectrum read from the
 // slot rs at the lane's pencil.  alpha(K) = D_M(e.K) - 1 and alpha'(K) =
 // D_M(e_perp.K) walk one row each of the LDS tables: along the lane's row
@@ -108,15 +115,14 @@ struct Item2D {
 // imaginary parts of one complex transform must be of the same size, or the
 // rounding of the larger one swamps the smaller.)
 template <int N>
-__device__ __forceinline__ void job2d_multiply(float2 (&z)[N], rsrc_t rs, int vspec, const JobDesc& J,
+__device__ __forceinline__ void job2d_multiply(float2 (&z)[N], const HalfSpec<N, N * 8>& hs, const JobDesc& J,
                                                const float* dtab, const float* atab, int j)
 {
-    constexpr int RS2 = N * 8;
     RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * j), modc<N>(J.e[1]));
     RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const float2 F = bload2(rs, vspec, k * RS2);
+        const float2 F = hs.get(k);
         const float al = a.get(), ap = b.get();
         z[k] = make_float2(__builtin_fmaf(al, F.x, -ap * F.y), __builtin_fmaf(al, F.y, ap * F.x));
         a.next();
@@ -130,13 +136,13 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
                                             const float* __restrict__ jobw, float dt, bool valid, float* xb,
                                             const float* dtab, int j)
 {
-    constexpr int RS = N * 4, RS2 = N * 8;   // element strides in bytes
+    constexpr int RS = N * 4;   // element stride in bytes
     float2 z[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
     fwd2d<N, RV>(z, xb, j);
-#pragma unroll
-    for (int k = 0; k < N; ++k) bstore2(z[k], it.fh, it.vspec, k * RS2);
+    const HalfSpec<N, N * 8> fh = half2d<N>(it.fh, it.vspec, j);
+    fh.put(z);
 
     // loss: l = Re IFFT(Lambda fhat); acc = -f l
 #pragma unroll
@@ -158,7 +164,7 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
-        job2d_multiply<N>(z, it.fh, it.vspec, J, dtab, atab, j);
+        job2d_multiply<N>(z, fh, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);
 #pragma unroll
         for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
@@ -240,9 +246,10 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
         QDVM_CHUNK_FENCE(i);
     }
     fwd2d<N, RV>(z, xb, j);
+    const HalfSpec<N, N * 8> gh = half2d<N>(rgh, it.vspec, j), fh = half2d<N>(it.fh, it.vspec, j);
+    gh.put(z);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        bstore2(z[k], rgh, it.vspec, k * RS2);
         const float l = bload(rlam, j * 4, k * RS);
         z[k].x *= l;
         z[k].y *= l;
@@ -258,9 +265,9 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
         for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, vc, i * RS), 0.f);
     }
     fwd2d<N, RV>(z, xb, j);
+    fh.put(z);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        bstore2(z[k], it.fh, it.vspec, k * RS2);
         const float l = bload(rlam, j * 4, k * RS);
         z[k].x *= l;
         z[k].y *= l;
@@ -286,13 +293,13 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
         float2 tg[N];
-        job2d_multiply<N>(tg, rgh, it.vspec, J, dtab, atab, j);
+        job2d_multiply<N>(tg, gh, J, dtab, atab, j);
         inv2d<N, RV>(tg, xb, j);                 // line(g) + i plane(g)
         if constexpr (STAGE) {
 #pragma unroll
             for (int i = 0; i < N; ++i) bstore2(tg[i], rtg, it.vspec, i * RS2);
         }
-        job2d_multiply<N>(z, it.fh, it.vspec, J, dtab, atab, j);
+        job2d_multiply<N>(z, fh, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);                  // line(f) + i plane(f)
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -325,17 +332,17 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
 #pragma unroll
     for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
     fwd2d<N, RV>(z, xb, j);
-#pragma unroll
-    for (int k = 0; k < N; ++k) bstore2(z[k], it.fh, it.vspec, k * RS2);
+    const HalfSpec<N, N * 8> fh = half2d<N>(it.fh, it.vspec, j), ch = half2d<N>(rch, it.vspec, j);
+    fh.put(z);
 #pragma unroll
     for (int i = 0; i < N; ++i)
         z[i] = make_float2(bload(rc, it.vcell, i * RS) * bload(it.f, it.vcell, i * RS), 0.f);
     fwd2d<N, RV>(z, xb, j);
+    ch.put(z);
     // IFFT(Lambda (fhat + i F(cf))) = l + i C_Lambda(cf)
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        bstore2(z[k], rch, it.vspec, k * RS2);
-        const float2 F = bload2(it.fh, it.vspec, k * RS2);
+        const float2 F = fh.get(k);
         const float l = bload(rlam, j * 4, k * RS);
         z[k] = make_float2(l * (F.x - z[k].y), l * (F.y + z[k].x));
         QDVM_CHUNK_FENCE(k);
@@ -356,8 +363,8 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
             RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const float2 F = bload2(it.fh, it.vspec, k * RS2);
-                const float2 C = bload2(rch, it.vspec, k * RS2);
+                const float2 F = fh.get(k);
+                const float2 C = ch.get(k);
                 const float al = a.get(), ap = b.get();
                 z[k] = make_float2(__builtin_fmaf(al, F.x, -ap * F.y), __builtin_fmaf(al, F.y, ap * F.x));
                 spart = __builtin_fmaf(al * ap, __builtin_fmaf(C.x, F.x, C.y * F.y), spart);

@@ -90,6 +90,16 @@ struct Cell3D {
     rsrc_t f, q, fh;
 };
 
+// Half-stored spectrum of one 3D cell slot at pencil pi = Kx n + Ky (mirror
+// pencil (-Kx, -Ky)).
+template <int N>
+__device__ __forceinline__ HalfSpec<N, N * N * 8> half3d(rsrc_t r, int pi)
+{
+    const int kx = pi / N, ky = pi % N;
+    const int mi = ((N - kx) % N) * N + (N - ky) % N;
+    return HalfSpec<N, N * N * 8>{r, pi * 8, mi * 8};
+}
+
 // z = (alpha + i alpha') * spectrum for one job (spectral layout: lane pencil
 // pi = Kx n + Ky, element k = Kz).  alpha(K) = D_M(e.K) - 1 walks one row of
 // the LDS table (its argument advances by e_2 per element); alpha' is the job's
@@ -99,15 +109,16 @@ template <int N, int T, int Q>
 __device__ __forceinline__ void job3d_multiply(float2 (&z)[Q][N], rsrc_t rs, const DevPlan& pl, const JobDesc& J,
                                                int jb, const float* atab, int tid)
 {
-    constexpr int NN = N * N, RS = NN * 4, RS2 = NN * 8;
+    constexpr int NN = N * N, RS = NN * 4;
     const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+        const HalfSpec<N, N * N * 8> hs = half3d<N>(rs, pi);
         RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            const float2 F = bload2(rs, pi * 8, k * RS2);
+            const float2 F = hs.get(k);
             const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
             z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
             a.next();
@@ -124,7 +135,7 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
                                             const float* dtab, int tid, int jb0 = 0, int jstep = 1,
                                             bool loss = true)
 {
-    constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
+    constexpr int NN = N * N, Q = NN / T, RS = NN * 4;
     float2 z[Q][N];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
@@ -132,12 +143,13 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
     float acc[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
     if (loss) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
                 const float l = bload(rlam, (tid + q * T) * 4, k * RS);
                 z[q][k].x *= l;
                 z[q][k].y *= l;
@@ -152,11 +164,10 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
-                acc[q][k] = 0.f;
-            }
+            for (int k = 0; k < N; ++k) acc[q][k] = 0.f;
     }
+    // the jobs read mirrored pencils of the spectrum, written by other threads
+    __syncthreads();
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = jb0; jb < pl.njobs; jb += jstep) {
@@ -257,10 +268,11 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
             z[q][x] = make_float2((float)((double)bload(cl.f, (tid + q * T) * 4, x * RS) - QDVM_MAXW3(q, x)), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
+    for (int q = 0; q < Q; ++q) half3d<N>(rgh, tid + q * T).put(z[q]);
+#pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            bstore2(z[q][k], rgh, (tid + q * T) * 8, k * RS2);
             const float l = bload(rlam, (tid + q * T) * 4, k * RS);
             z[q][k].x *= l;
             z[q][k].y *= l;
@@ -278,10 +290,11 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
+    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
+#pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
             const float l = bload(rlam, (tid + q * T) * 4, k * RS);
             z[q][k].x *= l;
             z[q][k].y *= l;
@@ -359,9 +372,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int k = 0; k < N; ++k) bstore2(z[q][k], cl.fh, (tid + q * T) * 8, k * RS2);
+    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -371,14 +382,15 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
             QDVM_CHUNK_FENCE(x);
         }
     fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) half3d<N>(rch, tid + q * T).put(z[q]);
     if (loss) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const int pi = tid + q * T;
-                bstore2(z[q][k], rch, pi * 8, k * RS2);
-                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
+                const float2 F = half3d<N>(cl.fh, pi).get(k);
                 const float l = bload(rlam, pi * 4, k * RS);
                 z[q][k] = make_float2(l * (F.x - z[q][k].y), l * (F.y + z[q][k].x));
                 QDVM_CHUNK_FENCE(k);
@@ -397,12 +409,10 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const int pi = tid + q * T;
-                bstore2(z[q][k], rch, pi * 8, k * RS2);
-                bstore(0.f, cl.q, pi * 4, k * RS);
-            }
+            for (int k = 0; k < N; ++k) bstore(0.f, cl.q, (tid + q * T) * 4, k * RS);
     }
+    // the jobs read mirrored pencils of both spectra, written by other threads
+    __syncthreads();
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = jb0; jb < pl.njobs; jb += jstep) {
@@ -413,11 +423,12 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi), ch = half3d<N>(rch, pi);
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const float2 F = bload2(cl.fh, pi * 8, k * RS2);
-                const float2 C = bload2(rch, pi * 8, k * RS2);
+                const float2 F = fh.get(k);
+                const float2 C = ch.get(k);
                 const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
                 z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
                 spart = __builtin_fmaf(al * a2, __builtin_fmaf(C.x, F.x, C.y * F.y), spart);

@@ -128,6 +128,28 @@ struct RowWalk {
     }
 };
 
+// Spectrum of a real field, stored as the half k <= n/2 of every pencil (a
+// contiguous half of the slot, so the working set of the spectral scratch is
+// halved): element k > n/2 of a pencil is the conjugate of element n - k of
+// the mirrored pencil (-K in the other axes), fhat(-K) = conj fhat(K).
+// STRIDE: byte distance between consecutive elements of a pencil.
+template <int N, int STRIDE>
+struct HalfSpec {
+    rsrc_t r;
+    int own, mir;   // byte offsets of the lane's pencil and of its mirror
+    __device__ __forceinline__ float2 get(int k) const
+    {
+        if (k <= N / 2) return bload2(r, own, k * STRIDE);
+        const float2 v = bload2(r, mir, (N - k) * STRIDE);
+        return make_float2(v.x, -v.y);
+    }
+    __device__ __forceinline__ void put(const float2 (&z)[N]) const
+    {
+#pragma unroll
+        for (int k = 0; k <= N / 2; ++k) bstore2(z[k], r, own, k * STRIDE);
+    }
+};
+
 // A byte offset unchanged, but opaque to the optimiser: a later read of a cell
 // through it is not merged with an earlier read of the same address, which
 // would keep the whole pencil alive in registers in between.
