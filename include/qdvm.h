@@ -192,8 +192,22 @@ qdvm_status qdvm_eval_batched(int32_t ncells, const qdvm_plan_t* cell_plan, cons
  * ordered. */
 qdvm_status qdvm_step_graph_create(qdvm_batch_t batch, float* f, float dt, hipStream_t capture_stream,
                                    qdvm_graph_t* out);
+
+/* The same with a choice of scheme:
+ *   QDVM_STEP_EULER  f <- f + dt Q(f)                      (as qdvm_step_graph_create)
+ *   QDVM_STEP_RK2    the two-stage TVD Runge-Kutta step the paper integrates
+ *                    with (Sec. 4): f1 = f + dt Q(f), f <- (f + f1 + dt Q(f1)) / 2.
+ *                    Each stage keeps f >= 0 when dt times the loss frequency
+ *                    is below 1 (Prop. 3.3) and the average is convex.  The
+ *                    graph owns a device buffer of the batch's extent for f1;
+ *                    only the cells are written (gaps keep their values).
+ * EINVAL for an unknown scheme. */
+#define QDVM_STEP_EULER 0
+#define QDVM_STEP_RK2 1
+qdvm_status qdvm_step_graph_create_scheme(qdvm_batch_t batch, float* f, float dt, int32_t scheme,
+                                          hipStream_t capture_stream, qdvm_graph_t* out);
 qdvm_status qdvm_step_graph_launch(qdvm_graph_t graph, hipStream_t stream);
-qdvm_status qdvm_step_graph_destroy(qdvm_graph_t graph);
+qdvm_status qdvm_step_graph_destroy(qdvm_graph_t graph);   /* synchronises the device first; NULL is a no-op */
 
 /* Kernel variant (FFT radix order) used by eval (op 0) and vjp (op 1):
  * -1 restores automatic choice.  qdvm_autotune times every variant on

