@@ -263,3 +263,32 @@ def test_3d_order2_direction_set(gpu_lib):
     errs = per_cell_rel_linf(q, oracle_q(plan, f), 16 ** 3)
     print("3D n=16 order 2: %.2e" % errs.max())
     assert errs.max() <= TOL
+
+
+@pytest.mark.parametrize("d,n,P,batch", [(2, 32, 16, 9), (2, 64, 8, 3), (3, 24, 16, 2), (3, 32, 8, 1)])
+def test_fft_variants_and_autotune(gpu_lib, d, n, P, batch):
+    # both radix orders of every transform give the operator (and its adjoint)
+    # to the tolerance; the autotuner keeps one of them
+    import torch
+    f = workloads.random_positive(70 + n, d, n, batch)
+    cot = np.random.default_rng(71).standard_normal(f.shape).astype(np.float32)
+    plan = gpu_lib.Plan(d, n, 8.0, num_dirs=P)
+    ref = oracle_q(plan, f)
+    from parity_util import oracle_vjp
+    rg, _ = oracle_vjp(plan, f, cot)
+    for v in (0, 1):
+        plan.set_variant(0, v)
+        plan.set_variant(1, v)
+        assert plan.get_variant(0) == v and plan.get_variant(1) == v
+        q = _eval(plan, f)
+        g, _ = plan.vjp(_dev(f), _dev(cot))
+        torch.cuda.synchronize()
+        eq = per_cell_rel_linf(q, ref, n ** d).max()
+        eg = per_cell_rel_linf(g.cpu().numpy(), rg, n ** d).max()
+        print("variant %d: eval %.2e vjp %.2e" % (v, eq, eg))
+        assert eq <= TOL and eg <= TOL
+    plan.autotune(batch)
+    assert plan.get_variant(0) in (0, 1) and plan.get_variant(1) in (0, 1)
+    assert per_cell_rel_linf(_eval(plan, f), ref, n ** d).max() <= TOL
+    with pytest.raises(gpu_lib.QdvmError):
+        plan.set_variant(0, 7)
