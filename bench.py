@@ -158,6 +158,29 @@ def batched_step(qdvm, workloads, torch, args):
     return out
 
 
+def profile_workload(args, qdvm, workloads, torch):
+    """One secondary workload alone: 3D n=32 P=16 on 2048 cells, its adjoint on
+    the 64-cell differentiation batch, or the captured batched Euler step."""
+    if args.profile_workload == "3d_n32_p16":
+        base3 = workloads.three_gaussians_batch(303, 64, 32)
+        f3 = torch.from_numpy(np.ascontiguousarray(np.tile(base3, (32, 1, 1, 1)))).cuda()
+        q3 = torch.empty_like(f3)
+        pl = qdvm.Plan(3, 32, 8.0, num_dirs=16)
+        t = time_calls(lambda: pl.eval(f3, out=q3), args.steps, args.warmup)
+        print(json.dumps({"workload": "3D n=32 P=16, 2048 cells", "ms": t}), flush=True)
+    elif args.profile_workload == "vjp_3d_n32_p16":
+        c5 = workloads.c5()
+        fv = torch.from_numpy(c5["f"]).cuda()
+        cv = torch.from_numpy(c5["cot"]).cuda()
+        pl = qdvm.Plan(3, 32, 8.0, num_dirs=16)
+        t = time_calls(lambda: pl.vjp(fv, cv), args.steps, args.warmup)
+        print(json.dumps({"workload": "adjoint 3D n=32 P=16, 64 cells", "ms": t}), flush=True)
+    else:
+        r = batched_step(qdvm, workloads, torch, args)
+        print(json.dumps({"workload": "batched Euler step, 4096 2D n=32 + 512 3D n=24 cells", "results": r}),
+              flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +191,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB elementwise copy (x*1 -> y) to scale HBM counters")
+    ap.add_argument("--profile-workload", choices=["3d_n32_p16", "vjp_3d_n32_p16", "c4_step"], default=None,
+                    help="run only this secondary workload's timed loop (for counter collection) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -181,6 +206,10 @@ def main():
     torch.cuda.set_device(0)
     qdvm.load()
     results = {}
+
+    if args.profile_workload:
+        profile_workload(args, qdvm, workloads, torch)
+        return
 
     # ---------------------------------------------------------------- headline
     B = args.batch
