@@ -210,7 +210,8 @@ qdvm_status qdvm_step_graph_launch(qdvm_graph_t graph, hipStream_t stream);
 qdvm_status qdvm_step_graph_destroy(qdvm_graph_t graph);   /* synchronises the device first; NULL is a no-op */
 
 /* Kernel variant (FFT radix order) used by eval (op 0) and vjp (op 1):
- * -1 restores automatic choice.  qdvm_autotune times every variant on
+ * -1 restores the built-in default (4 x 8 pencils for 3D n = 32, else
+ * variant 0).  qdvm_autotune times every variant on
  * `batch` synthetic cells on `stream` and keeps the fastest per op. */
 qdvm_status qdvm_set_variant(qdvm_plan_t plan, int32_t op, int32_t variant);
 qdvm_status qdvm_get_variant(qdvm_plan_t plan, int32_t op, int32_t* variant);

@@ -188,7 +188,10 @@ qdvm::DevScratch scratch_of(const qdvm::HostPlan& hp, const WsLayout& L, bool ad
     return s;
 }
 
-int effective_variant(const qdvm_plan_s* p, int op) { return p->variant[op] >= 0 ? p->variant[op] : 0; }
+int effective_variant(const qdvm_plan_s* p, int op)
+{
+    return p->variant[op] >= 0 ? p->variant[op] : qdvm::default_variant(p->hp.dim, p->hp.n);
+}
 
 qdvm_status do_eval(qdvm_plan_s* p, int batch, const float* f, float* q, const float* w, float dt,
                     hipStream_t st, int variant)

@@ -24,12 +24,15 @@ __device__ __forceinline__ int addr3(int pi, int e)
     return a * SX + b * SY + e;
 }
 
-template <int N, int T, int Q, int PA, int PB>
+// Exchange between two phases through the padded LDS cube, real parts then
+// imaginary parts.  LEAD: begin with a workgroup barrier (needed when another
+// wave may still be reading the rows this one writes).
+template <int N, int T, int Q, int PA, int PB, bool LEAD = true>
 __device__ __forceinline__ void block_transpose(float2 (&z)[Q][N], float* xb, int tid)
 {
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
-        __syncthreads();
+        if (part || LEAD) __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -46,6 +49,38 @@ __device__ __forceinline__ void block_transpose(float2 (&z)[Q][N], float* xb, in
     }
 }
 
+// Phases Y and Z give a lane the same x (pencil pi = x n + b in both).  When n
+// divides 64 the n lanes of an x-slab sit in one wave, so the Y <-> Z exchange
+// only touches the LDS rows x of the wave's own slabs and needs no workgroup
+// barrier; phase X <-> Y changes the slab of a lane and stays block-wide.
+template <int N>
+constexpr bool local_yz() { return 64 % N == 0; }
+
+template <int N, int T, int Q, int PA, int PB>
+__device__ __forceinline__ void wave_transpose(float2 (&z)[Q][N], float* xb, int tid)
+{
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        if (part) wave_sync();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < N; ++e) xb[addr3<N, PA>(tid + q * T, e)] = part ? z[q][e].y : z[q][e].x;
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const float v = xb[addr3<N, PB>(tid + q * T, e)];
+                if (part) z[q][e].y = v;
+                else z[q][e].x = v;
+            }
+    }
+}
+
+// Forward: X -> Y block-wide (it begins with a barrier: the previous phase may
+// have read any row), Y -> Z inside the wave (after the X -> Y reads each wave
+// only touches its own rows).
 template <int N, int T, int Q, int RV>
 __device__ __forceinline__ void fwd3d(float2 (&z)[Q][N], float* xb, int tid)
 {
@@ -54,20 +89,29 @@ __device__ __forceinline__ void fwd3d(float2 (&z)[Q][N], float* xb, int tid)
     block_transpose<N, T, Q, 0, 1>(z, xb, tid);
 #pragma unroll
     for (int q = 0; q < Q; ++q) fftp<N, RV, -1>(z[q]);
-    block_transpose<N, T, Q, 1, 2>(z, xb, tid);
+    if constexpr (local_yz<N>()) wave_transpose<N, T, Q, 1, 2>(z, xb, tid);
+    else block_transpose<N, T, Q, 1, 2>(z, xb, tid);
 #pragma unroll
     for (int q = 0; q < Q; ++q) fftp<N, RV, -1>(z[q]);
 }
 
+// Inverse: one barrier, then Z -> Y inside the wave and Y -> X block-wide
+// (whose first writes go to the wave's own rows, so it needs no leading
+// barrier of its own).
 template <int N, int T, int Q, int RV>
 __device__ __forceinline__ void inv3d(float2 (&z)[Q][N], float* xb, int tid)
 {
 #pragma unroll
     for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
-    block_transpose<N, T, Q, 2, 1>(z, xb, tid);
+    if constexpr (local_yz<N>()) {
+        __syncthreads();
+        wave_transpose<N, T, Q, 2, 1>(z, xb, tid);
+    } else {
+        block_transpose<N, T, Q, 2, 1>(z, xb, tid);
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
-    block_transpose<N, T, Q, 1, 0>(z, xb, tid);
+    block_transpose<N, T, Q, 1, 0, !local_yz<N>()>(z, xb, tid);
 #pragma unroll
     for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
 }
@@ -122,27 +166,34 @@ __device__ __forceinline__ void job3d_multiply(float2 (&z)[Q][N], rsrc_t rs, con
             const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
             z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
             a.next();
-            QDVM_CHUNK_FENCE(k);
+            // n = 32, one pencil per lane: chunks of 4 loads keep the job loop
+            // inside the 128-register cap
+            if (((k & 3) == 3 && N == 32 && Q == 1) || (k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
 
-template <int N, int T, int RV>
 // Jobs jb0, jb0 + jstep, ... of the direction loop; the loss only if `loss`
 // (a cell whose jobs are spread over several workgroups: each writes its part).
+// The last LACC elements of each lane's gain accumulator live in LDS (`lacc`,
+// LACC x T*Q floats, each lane touching only its own words) instead of
+// registers: at n = 32 with one pencil per lane the register cap would
+// otherwise spill them to scratch memory around every job.
+template <int N, int T, int RV, int LACC = 0>
 __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl, rsrc_t rlam,
                                             const float* __restrict__ jobw, float dt, float* xb,
                                             const float* dtab, int tid, int jb0 = 0, int jstep = 1,
-                                            bool loss = true)
+                                            bool loss = true, float* lacc = nullptr)
 {
-    constexpr int NN = N * N, Q = NN / T, RS = NN * 4;
+    constexpr int NN = N * N, Q = NN / T, RS = NN * 4, NR = N - LACC;
     float2 z[Q][N];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
-    float acc[Q][N];
+    float acc[Q][NR > 0 ? NR : 1];
+    auto lslot = [&](int q, int x) -> float& { return lacc[(x - NR) * (T * Q) + tid + q * T]; };
 #pragma unroll
     for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
     if (loss) {
@@ -159,12 +210,19 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int x = 0; x < N; ++x) acc[q][x] = -bload(cl.f, (tid + q * T) * 4, x * RS) * z[q][x].x;
+            for (int x = 0; x < N; ++x) {
+                const float v = -bload(cl.f, (tid + q * T) * 4, x * RS) * z[q][x].x;
+                if (x < NR) acc[q][x] = v;
+                else lslot(q, x) = v;
+            }
     } else {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int k = 0; k < N; ++k) acc[q][k] = 0.f;
+            for (int k = 0; k < N; ++k) {
+                if (k < NR) acc[q][k] = 0.f;
+                else lslot(q, k) = 0.f;
+            }
     }
     // the jobs read mirrored pencils of the spectrum, written by other threads
     __syncthreads();
@@ -178,14 +236,18 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int x = 0; x < N; ++x) acc[q][x] = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, acc[q][x]);
+            for (int x = 0; x < N; ++x) {
+                if (x < NR) acc[q][x] = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, acc[q][x]);
+                else lslot(q, x) = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, lslot(q, x));
+            }
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int x = 0; x < N; ++x) {
             const int v = (tid + q * T) * 4;
-            bstore(dt == 0.f ? acc[q][x] : __builtin_fmaf(dt, acc[q][x], bload(cl.f, v, x * RS)), cl.q, v, x * RS);
+            const float a = x < NR ? acc[q][x] : lslot(q, x);
+            bstore(dt == 0.f ? a : __builtin_fmaf(dt, a, bload(cl.f, v, x * RS)), cl.q, v, x * RS);
         }
 }
 
@@ -454,7 +516,9 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            // the multipliers are read again rather than kept from the first
+            // multiply: holding them through two transforms would spill
+            const int pi = reread(tid + q * T), kx = pi / N, ky = pi % N;
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
             for (int k = 0; k < N; ++k) {

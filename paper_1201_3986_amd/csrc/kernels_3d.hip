@@ -28,6 +28,16 @@
 
 namespace qdvm {
 
+// Gain-accumulator elements per lane kept in LDS by the plain evaluation (the
+// LDS behind the Dirichlet tables, shared with the reduction slots that only
+// the other cell routines use).  n = 32 with one pencil per lane: 6 x 1024
+// floats fit beside the transpose cube and the largest table (Nt = 15).
+template <int N, int T>
+constexpr int lacc3d()
+{
+    return (N == 32 && T == 1024) ? 6 : 0;
+}
+
 template <int N, int T, int RV, bool SPLIT>
 __global__ __launch_bounds__(T) void k_eval3d(DevPlan pl, int batch, const float* f, float* q, float dt,
                                               DevScratch s)
@@ -54,7 +64,8 @@ __global__ __launch_bounds__(T) void k_eval3d(DevPlan pl, int batch, const float
         if constexpr (SPLIT)
             cell3d_eval_split<N, T, RV, STAGE>(pl, cl, rgh, rtg, rlam, s.jobw, dt, xb, red, dtab, tid);
         else
-            cell3d_eval<N, T, RV>(pl, cl, rlam, s.jobw, dt, xb, dtab, tid);
+            cell3d_eval<N, T, RV, lacc3d<N, T>()>(pl, cl, rlam, s.jobw, dt, xb, dtab, tid, 0, 1, true,
+                                                  dtab + dtab_floats(pl));
     }
 }
 
@@ -109,7 +120,8 @@ __global__ __launch_bounds__(T) void k_eval3d_js(DevPlan pl, int batch, int G, c
     cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
     cl.q = make_rsrc(s.part + ((size_t)g * batch + cell) * NPTS, NPTS * 4);
     cl.fh = make_rsrc(s.spec + (size_t)blockIdx.x * NPTS, NPTS * 8);
-    cell3d_eval<N, T, RV>(pl, cl, make_rsrc(s.lam, NPTS * 4), s.jobw, 0.f, xb, dtab, tid, g, G, g == 0);
+    cell3d_eval<N, T, RV, lacc3d<N, T>()>(pl, cl, make_rsrc(s.lam, NPTS * 4), s.jobw, 0.f, xb, dtab, tid, g, G,
+                                          g == 0, dtab + dtab_floats(pl));
 }
 
 template <int N, int T, int RV>
@@ -221,6 +233,10 @@ int device_cu_count()
 
 int num_variants(int, int) { return 2; }
 
+// Radix order used when none is set: 3D n = 32 runs 4 x 8 pencils (fewer live
+// registers in the one-pencil-per-lane job loop than 8 x 4), else variant 0.
+int default_variant(int dim, int n) { return (dim == 3 && n == 32) ? 1 : 0; }
+
 namespace {
 
 template <int N>
@@ -229,12 +245,22 @@ constexpr int t3d()
     return N == 32 ? 1024 : (N == 24 ? 576 : (N == 16 ? 256 : 64));
 }
 
-// transpose buffer | Dirichlet tables | reduction slots (5 doubles per wave) and n Maxwellian factors
+// The adjoint keeps more live values per pencil than the evaluation: at n = 32
+// two pencils per lane (512 threads, 256 registers) instead of one pencil per
+// lane under a 128-register cap, which spills.
 template <int N>
+constexpr int t3d_vjp()
+{
+    return N == 32 ? 512 : t3d<N>();
+}
+
+// transpose buffer | Dirichlet tables | reduction slots (5 doubles per wave) and n Maxwellian
+// factors, or the gain-accumulator elements of the plain evaluation
+template <int N, int T = t3d<N>()>
 size_t lds3d(int ntilde)
 {
-    constexpr int T = t3d<N>();
-    return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)2 * (ntilde + 1) * N + 2 * (5 * ((T + 63) / 64) + N));
+    const size_t tail = std::max<size_t>(2 * (5 * ((T + 63) / 64) + N), (size_t)lacc3d<N, T>() * T);
+    return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)2 * (ntilde + 1) * N + tail);
 }
 
 // Spread each cell's direction loop over G workgroups when the batch leaves
@@ -335,9 +361,9 @@ LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant)
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d<N>();
+                constexpr int T = t3d_vjp<N>();
                 li.block = T;
-                li.lds = lds3d<N>(pl.ntilde);
+                li.lds = lds3d<N, T>(pl.ntilde);
                 e = variant ? occupancy_grid(k_vjp3d<N, T, 1>, T, li.lds, batch, li.grid)
                             : occupancy_grid(k_vjp3d<N, T, 0>, T, li.lds, batch, li.grid);
                 li.slots = li.grid;
@@ -367,7 +393,7 @@ hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float*
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d<N>();
+                constexpr int T = t3d_vjp<N>();
                 if (li.jsplit > 1) {
                     if (variant)
                         hipLaunchKernelGGL((k_vjp3d_js<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch,

@@ -154,6 +154,7 @@ hipError_t launch_average_cells(const int64_t* off, const int32_t* cnt, int ncel
                                 hipStream_t st);
 
 int num_variants(int dim, int n);
+int default_variant(int dim, int n);
 int device_cu_count();
 
 }  // namespace qdvm
