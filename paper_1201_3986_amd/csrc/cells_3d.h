@@ -116,10 +116,27 @@ __device__ __forceinline__ void inv3d(float2 (&z)[Q][N], float* xb, int tid)
     for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
 }
 
+// Sum over the 64 lanes of a wave (uniform result): xor swizzles within each
+// half, then the two halves.  Nothing lane-dependent stays live between calls.
+__device__ __forceinline__ float wave_sum(float v)
+{
+#define QDVM_SWZ_ADD(pat) \
+    v += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), pat))
+    QDVM_SWZ_ADD(0x041F);   // and 0x1f, xor 1
+    QDVM_SWZ_ADD(0x081F);   // xor 2
+    QDVM_SWZ_ADD(0x101F);   // xor 4
+    QDVM_SWZ_ADD(0x201F);   // xor 8
+    QDVM_SWZ_ADD(0x401F);   // xor 16
+#undef QDVM_SWZ_ADD
+    const int a = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0);
+    const int b = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32);
+    return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+}
+
 template <int N, int T, int Q>
 __device__ __forceinline__ float block_sum(float v, float* red, int tid)
 {
-    v = group_sum<64>(v);
+    v = wave_sum(v);
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
@@ -144,6 +161,14 @@ __device__ __forceinline__ HalfSpec<N, N * N * 8> half3d(rsrc_t r, int pi)
     return HalfSpec<N, N * N * 8>{r, pi * 8, mi * 8};
 }
 
+// Load-chunk fence of the job loops: at n = 32 with one pencil per lane,
+// chunks of 4 keep the loop inside the 128-register cap.
+#define QDVM_FENCE3(k)                                                                      \
+    do {                                                                                    \
+        if (((k) & 3) == 3 && N == 32 && Q == 1) __builtin_amdgcn_sched_barrier(0);         \
+        else QDVM_CHUNK_FENCE(k);                                                           \
+    } while (0)
+
 // z = (alpha + i alpha') * spectrum for one job (spectral layout: lane pencil
 // pi = Kx n + Ky, element k = Kz).  alpha(K) = D_M(e.K) - 1 walks one row of
 // the LDS table (its argument advances by e_2 per element); alpha' is the job's
@@ -166,9 +191,7 @@ __device__ __forceinline__ void job3d_multiply(float2 (&z)[Q][N], rsrc_t rs, con
             const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
             z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
             a.next();
-            // n = 32, one pencil per lane: chunks of 4 loads keep the job loop
-            // inside the 128-register cap
-            if (((k & 3) == 3 && N == 32 && Q == 1) || (k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            QDVM_FENCE3(k);
         }
     }
 }
@@ -409,18 +432,53 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
         }
 }
 
+// um[q][r] = z of the mirror pencil (-Kx, -Ky) at element (n - r) mod n, i.e.
+// uhat(-K) for K = (Kx, Ky, r), r = 0..n/2, through the LDS cube (real parts,
+// then imaginary parts; each lane writes the elements its mirror lane needs).
+template <int N, int T, int Q>
+__device__ __forceinline__ void mirror_exchange(const float2 (&z)[Q][N], float2 (&um)[Q][N / 2 + 1], float* xb,
+                                                int tid)
+{
+    constexpr int NN = N * N;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int r = 0; r <= N / 2; ++r) {
+                const float2 v = z[q][(N - r) % N];
+                xb[r * NN + tid + q * T] = part ? v.y : v.x;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            const int mi = ((N - kx) % N) * N + (N - ky) % N;
+#pragma unroll
+            for (int r = 0; r <= N / 2; ++r) {
+                const float v = xb[r * NN + mi];
+                if (part) um[q][r].y = v;
+                else um[q][r].x = v;
+            }
+        }
+    }
+}
+
 // Adjoint of one cell.  With c the cotangent and unnormalised transforms F:
 //   l + i C(cf) = IFFT(Lambda (fhat + i F(cf)))            (both real)
 //   per job:  u + i v = IFFT((a + i a') fhat) = n^d (g + i h)
 //             dQ/dw_j part: <c, g h> - <cf, l_j>, the second term by Parseval:
-//             n^{-2d} sum_x c u v - n^{-d} sum_K a a' Re(conj(F(cf)) fhat)
+//             n^{-2d} sum_x c u v - n^{-d} sum_K a a' R(K),
+//             R = Re(conj(F(cf)) fhat)  (real and even: stored as half pencils)
 //             S += W_j / n^{2d} (a - i a') F(c v + i c u)
 //   grad_f = Re IFFT(S) - c l - C(cf)
 // which uses A(c h) + B(c g) = Re IFFT((a - i a') F(c h + i c g)), valid because
 // the multipliers a = alpha_j and a' = alpha'_j are real and even.
-template <int N, int T, int RV>
 // Jobs jb0, jb0 + jstep, ...; the loss part only if `loss` (see cell3d_eval).
-__device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, rsrc_t rc, rsrc_t rch,
+// rr: R of the cell (half pencils, 4 bytes per element).
+template <int N, int T, int RV>
+__device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, rsrc_t rc, rsrc_t rr,
                                            rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
                                            float* __restrict__ gwp, float inv_n2, float inv_n, float* xb,
                                            float* red, const float* dtab, int tid, int jb0 = 0, int jstep = 1,
@@ -441,11 +499,19 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         for (int x = 0; x < N; ++x) {
             const int v = (tid + q * T) * 4;
             z[q][x] = make_float2(bload(rc, v, x * RS) * bload(cl.f, v, x * RS), 0.f);
-            QDVM_CHUNK_FENCE(x);
+            QDVM_FENCE3(x);
         }
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) half3d<N>(rch, tid + q * T).put(z[q]);
+    for (int q = 0; q < Q; ++q) {
+        const int pi = tid + q * T;
+        const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi);
+#pragma unroll
+        for (int k = 0; k <= N / 2; ++k) {   // own half of the pencil: written by this lane
+            const float2 F = fh.get(k);
+            bstore(__builtin_fmaf(z[q][k].x, F.x, z[q][k].y * F.y), rr, pi * 4, k * RS);
+        }
+    }
     if (loss) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
@@ -455,7 +521,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
                 const float2 F = half3d<N>(cl.fh, pi).get(k);
                 const float l = bload(rlam, pi * 4, k * RS);
                 z[q][k] = make_float2(l * (F.x - z[q][k].y), l * (F.y + z[q][k].x));
-                QDVM_CHUNK_FENCE(k);
+                QDVM_FENCE3(k);
             }
         inv3d<N, T, Q, RV>(z, xb, tid);
         // -c l - C(cf) goes to grad_f now and is completed after the direction
@@ -473,7 +539,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
             for (int k = 0; k < N; ++k) bstore(0.f, cl.q, (tid + q * T) * 4, k * RS);
     }
-    // the jobs read mirrored pencils of both spectra, written by other threads
+    // the jobs read mirrored pencils of the spectrum and of R, written by other threads
     __syncthreads();
 
     const float* atab = dtab_alpha(dtab, pl);
@@ -485,17 +551,18 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int pi = tid + q * T, kx = pi / N, ky = pi % N;
-            const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi), ch = half3d<N>(rch, pi);
+            const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi);
+            const int rown = pi * 4, rmir = fh.mir / 2;
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const float2 F = fh.get(k);
-                const float2 C = ch.get(k);
+                const float R = k <= N / 2 ? bload(rr, rown, k * RS) : bload(rr, rmir, (N - k) * RS);
                 const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
                 z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
-                spart = __builtin_fmaf(al * a2, __builtin_fmaf(C.x, F.x, C.y * F.y), spart);
+                spart = __builtin_fmaf(al * a2, R, spart);
                 a.next();
-                QDVM_CHUNK_FENCE(k);
+                QDVM_FENCE3(k);
             }
         }
         inv3d<N, T, Q, RV>(z, xb, tid);
@@ -508,12 +575,17 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
                 const float c = bload(rc, v, x * RS);
                 rpart = __builtin_fmaf(c * z[q][x].x, z[q][x].y, rpart);
                 z[q][x] = make_float2(c * z[q][x].y, c * z[q][x].x);
-                QDVM_CHUNK_FENCE(x);
+                QDVM_FENCE3(x);
             }
         }
         const float tot = block_sum<N, T, Q>(rpart * inv_n2 - spart * inv_n, red, tid);
         if (tid == 0) gwp[jb] = tot;
         fwd3d<N, T, Q, RV>(z, xb, tid);
+        // Only the Hermitian part of (a - i a') uhat reaches Re IFFT(S), so S is
+        // kept as that part, in half pencils: it needs uhat(-K), held by the
+        // mirror lane and exchanged through LDS.
+        float2 um[Q][N / 2 + 1];
+        mirror_exchange<N, T, Q>(z, um, xb, tid);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             // the multipliers are read again rather than kept from the first
@@ -521,10 +593,12 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
             const int pi = reread(tid + q * T), kx = pi / N, ky = pi % N;
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const float al = cw * a.get(), a2 = cw * bload(rap, pi * 4, k * RS);
-                float2 t = make_float2(__builtin_fmaf(al, z[q][k].x, a2 * z[q][k].y),
-                                       __builtin_fmaf(al, z[q][k].y, -a2 * z[q][k].x));
+            for (int k = 0; k <= N / 2; ++k) {
+                const float al = 0.5f * cw * a.get(), a2 = 0.5f * cw * bload(rap, pi * 4, k * RS);
+                // (a/2)(u + conj m) - i (a'/2)(u - conj m), m = uhat(-K)
+                const float2 u = z[q][k], m = um[q][k];
+                float2 t = make_float2(__builtin_fmaf(al, u.x + m.x, a2 * (u.y + m.y)),
+                                       __builtin_fmaf(al, u.y - m.y, -a2 * (u.x - m.x)));
                 if (jb > jb0) {
                     const float2 sv = bload2(rsh, pi * 8, k * RS2);
                     t.x += sv.x;
@@ -532,15 +606,19 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
                 }
                 bstore2(t, rsh, pi * 8, k * RS2);
                 a.next();
-                QDVM_CHUNK_FENCE(k);
+                QDVM_FENCE3(k);
             }
         }
     }
     if (jb0 < pl.njobs) {
+        // the other half of each pencil is the mirror lane's
+        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
+        for (int q = 0; q < Q; ++q) {
+            const HalfSpec<N, N * N * 8> sh = half3d<N>(rsh, tid + q * T);
 #pragma unroll
-            for (int k = 0; k < N; ++k) z[q][k] = bload2(rsh, (tid + q * T) * 8, k * RS2);
+            for (int k = 0; k < N; ++k) z[q][k] = sh.get(k);
+        }
         inv3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
         for (int q = 0; q < Q; ++q)

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(T) void k_vjp3d(DevPlan pl, int batch, const float*
     const float inv_n = 1.f / (float)NPTS;
     const float inv_n2 = inv_n * inv_n;
     const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
-    const rsrc_t rch = make_rsrc(s.spec2 + slot, NPTS * 8);
+    const rsrc_t rr = make_rsrc(s.spec2 + slot, NPTS * 8);
     const rsrc_t rsh = make_rsrc(s.acc + slot, NPTS * 8);
     Cell3D cl;
     cl.fh = make_rsrc(s.spec + slot, NPTS * 8);
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(T) void k_vjp3d(DevPlan pl, int batch, const float*
         cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
         cl.q = make_rsrc(g + (size_t)cell * NPTS, NPTS * 4);
         const rsrc_t rc = make_rsrc(c + (size_t)cell * NPTS, NPTS * 4);
-        cell3d_vjp<N, T, RV>(pl, cl, rc, rch, rsh, rlam, s.jobw, s.gw_part + (size_t)cell * pl.njobs, inv_n2,
+        cell3d_vjp<N, T, RV>(pl, cl, rc, rr, rsh, rlam, s.jobw, s.gw_part + (size_t)cell * pl.njobs, inv_n2,
                              inv_n, xb, red, dtab, tid);
     }
 }
@@ -245,15 +245,6 @@ constexpr int t3d()
     return N == 32 ? 1024 : (N == 24 ? 576 : (N == 16 ? 256 : 64));
 }
 
-// The adjoint keeps more live values per pencil than the evaluation: at n = 32
-// two pencils per lane (512 threads, 256 registers) instead of one pencil per
-// lane under a 128-register cap, which spills.
-template <int N>
-constexpr int t3d_vjp()
-{
-    return N == 32 ? 512 : t3d<N>();
-}
-
 // transpose buffer | Dirichlet tables | reduction slots (5 doubles per wave) and n Maxwellian
 // factors, or the gain-accumulator elements of the plain evaluation
 template <int N, int T = t3d<N>()>
@@ -361,7 +352,7 @@ LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant)
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d_vjp<N>();
+                constexpr int T = t3d<N>();
                 li.block = T;
                 li.lds = lds3d<N, T>(pl.ntilde);
                 e = variant ? occupancy_grid(k_vjp3d<N, T, 1>, T, li.lds, batch, li.grid)
@@ -393,7 +384,7 @@ hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float*
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d_vjp<N>();
+                constexpr int T = t3d<N>();
                 if (li.jsplit > 1) {
                     if (variant)
                         hipLaunchKernelGGL((k_vjp3d_js<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch,
