@@ -175,7 +175,9 @@ qdvm_status qdvm_vjp(qdvm_plan_t plan, int32_t batch, const float* f, const floa
 qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const int64_t* cell_offset,
                             qdvm_batch_t* out);
 qdvm_status qdvm_batch_destroy(qdvm_batch_t batch);   /* synchronises the device first; NULL is a no-op */
-/* launches (kernel launches per evaluation), work items, algorithmic FLOPs of one evaluation;
+/* launches (kernel launches per evaluation: one per block-size family, plus a
+ * queue-counter reset before a family whose items differ in cost), work
+ * items, algorithmic FLOPs of one evaluation;
  * each output may be NULL */
 qdvm_status qdvm_batch_info(qdvm_batch_t batch, int32_t* launches, int32_t* items, double* flops);
 /* q = Q(f) per cell (dt == 0) or q = f + dt Q(f); f and q are device arrays

@@ -672,7 +672,9 @@ qdvm_status qdvm_batch_info(qdvm_batch_t b, int32_t* launches, int32_t* items, d
     if (!b) return fail(QDVM_EINVAL, "null batch");
     int32_t n = 0;
     for (auto& F : b->fams) n += (int32_t)F.items.size();
-    if (launches) *launches = (int32_t)b->fams.size();
+    int32_t nl = 0;
+    for (auto& F : b->fams) nl += 1 + (qdvm::batch_uses_counter(F.dev) ? 1 : 0);
+    if (launches) *launches = nl;
     if (items) *items = n;
     if (flops) *flops = b->flops;
     return QDVM_OK;

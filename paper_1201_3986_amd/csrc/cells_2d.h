@@ -155,8 +155,14 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
     float acc[N];
     {
         const int vc = reread(it.vcell);
+        constexpr int C = N < 16 ? N : 16;
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc[i] = -bload(it.f, vc, i * RS) * z[i].x;
+        for (int i0 = 0; i0 < N; i0 += C) {
+            float fv[C];
+            load_run<C>(fv, it.f, vc, i0, RS);
+#pragma unroll
+            for (int i = 0; i < C; ++i) acc[i0 + i] = -fv[i] * z[i0 + i].x;
+        }
     }
 
     // direction loop: g + i h = IFFT((alpha + i alpha') fhat), acc += W g h
@@ -175,9 +181,10 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
 #pragma unroll
         for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
     } else {
-        const int vc = reread(it.vcell);
+        float fv[N];
+        load_run<N>(fv, it.f, reread(it.vcell), 0, RS);
 #pragma unroll
-        for (int i = 0; i < N; ++i) bstore(__builtin_fmaf(dt, acc[i], bload(it.f, vc, i * RS)), it.q, it.vcell, i * RS);
+        for (int i = 0; i < N; ++i) bstore(__builtin_fmaf(dt, acc[i], fv[i]), it.q, it.vcell, i * RS);
     }
 }
 
@@ -314,9 +321,10 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
 #pragma unroll
         for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
     } else {
-        const int vc = reread(it.vcell);
+        float fv[N];
+        load_run<N>(fv, it.f, reread(it.vcell), 0, RS);
 #pragma unroll
-        for (int i = 0; i < N; ++i) bstore(__builtin_fmaf(dt, acc[i], bload(it.f, vc, i * RS)), it.q, it.vcell, i * RS);
+        for (int i = 0; i < N; ++i) bstore(__builtin_fmaf(dt, acc[i], fv[i]), it.q, it.vcell, i * RS);
     }
 }
 
@@ -350,8 +358,12 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
     inv2d<N, RV>(z, xb, j);
     // -c l - C(cf) goes to grad_f now and is completed after the direction
     // loop, so that no pencil-sized accumulator stays live through it
+    {
+        float cv[N];
+        load_run<N>(cv, rc, it.vcell, 0, RS);
 #pragma unroll
-    for (int i = 0; i < N; ++i) bstore(-bload(rc, it.vcell, i * RS) * z[i].x - z[i].y, it.q, it.vcell, i * RS);
+        for (int i = 0; i < N; ++i) bstore(-cv[i] * z[i].x - z[i].y, it.q, it.vcell, i * RS);
+    }
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
@@ -412,8 +424,12 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
 #pragma unroll
         for (int k = 0; k < N; ++k) z[k] = bload2(rsh, it.vspec, k * RS2);
         inv2d<N, RV>(z, xb, j);
+        {
+            float gv[N];
+            load_run<N>(gv, it.q, it.vcell, 0, RS);
 #pragma unroll
-        for (int i = 0; i < N; ++i) bstore(bload(it.q, it.vcell, i * RS) + z[i].x, it.q, it.vcell, i * RS);
+            for (int i = 0; i < N; ++i) bstore(gv[i] + z[i].x, it.q, it.vcell, i * RS);
+        }
     }
 }
 

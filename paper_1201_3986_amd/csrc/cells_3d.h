@@ -161,12 +161,18 @@ __device__ __forceinline__ HalfSpec<N, N * N * 8> half3d(rsrc_t r, int pi)
     return HalfSpec<N, N * N * 8>{r, pi * 8, mi * 8};
 }
 
-// Load-chunk fence of the job loops: at n = 32 with one pencil per lane,
-// chunks of 4 keep the loop inside the 128-register cap.
+// Elements per load chunk of the job multiply: at n = 32 with one pencil per
+// lane, chunks of 4 keep the loop inside the 128-register cap; at n = 24 (nine
+// waves per CU, registers to spare) half a pencil is read at once (measured
+// best of 8, 12 and 24 in the batched kernel).  The other
+// loops fence every 4 or 8 elements (QDVM_FENCE3).
+template <int N, int Q>
+constexpr int chunk3() { return (N == 32 && Q == 1) ? 4 : (N == 24 ? 12 : 8); }
+
 #define QDVM_FENCE3(k)                                                                      \
     do {                                                                                    \
-        if (((k) & 3) == 3 && N == 32 && Q == 1) __builtin_amdgcn_sched_barrier(0);         \
-        else QDVM_CHUNK_FENCE(k);                                                           \
+        if (((k) & (chunk3<N, Q>() == 4 ? 3 : 7)) == (chunk3<N, Q>() == 4 ? 3 : 7))          \
+            __builtin_amdgcn_sched_barrier(0);                                              \
     } while (0)
 
 // z = (alpha + i alpha') * spectrum for one job (spectral layout: lane pencil
@@ -174,7 +180,10 @@ __device__ __forceinline__ HalfSpec<N, N * N * 8> half3d(rsrc_t r, int pi)
 // the LDS table (its argument advances by e_2 per element); alpha' is the job's
 // FP64-built plane table.  The job weight is applied to the product (see
 // job2d_multiply).
-template <int N, int T, int Q>
+// C: elements per load chunk, each chunk's reads issued before their use; 4 or
+// less: reads interleaved with their use, fenced every 4 or 8 elements (the
+// near-equilibrium cell, which holds two transforms, uses chunks of 8).
+template <int N, int T, int Q, int C = chunk3<N, Q>()>
 __device__ __forceinline__ void job3d_multiply(float2 (&z)[Q][N], rsrc_t rs, const DevPlan& pl, const JobDesc& J,
                                                int jb, const float* atab, int tid)
 {
@@ -185,13 +194,35 @@ __device__ __forceinline__ void job3d_multiply(float2 (&z)[Q][N], rsrc_t rs, con
         const int pi = tid + q * T, kx = pi / N, ky = pi % N;
         const HalfSpec<N, N * N * 8> hs = half3d<N>(rs, pi);
         RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
+        if constexpr (C <= 4) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const float2 F = hs.get(k);
-            const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
-            z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
-            a.next();
-            QDVM_FENCE3(k);
+            for (int k = 0; k < N; ++k) {
+                const float2 F = hs.get(k);
+                const float al = a.get(), a2 = bload(rap, pi * 4, k * RS);
+                z[q][k] = make_float2(__builtin_fmaf(al, F.x, -a2 * F.y), __builtin_fmaf(al, F.y, a2 * F.x));
+                a.next();
+                QDVM_FENCE3(k);
+            }
+        } else {
+#pragma unroll
+            for (int k0 = 0; k0 < N; k0 += C) {
+                float2 F[C];
+                float a2[C];
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    F[i] = hs.get(k0 + i);
+                    a2[i] = bload(rap, pi * 4, (k0 + i) * RS);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const float al = a.get();
+                    z[q][k0 + i] = make_float2(__builtin_fmaf(al, F[i].x, -a2[i] * F[i].y),
+                                               __builtin_fmaf(al, F[i].y, a2[i] * F[i].x));
+                    a.next();
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
 }
@@ -230,13 +261,20 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
                 QDVM_CHUNK_FENCE(k);
             }
         inv3d<N, T, Q, RV>(z, xb, tid);
+        constexpr int C = N % 8 == 0 ? 8 : N;
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int x = 0; x < N; ++x) {
-                const float v = -bload(cl.f, (tid + q * T) * 4, x * RS) * z[q][x].x;
-                if (x < NR) acc[q][x] = v;
-                else lslot(q, x) = v;
+            for (int x0 = 0; x0 < N; x0 += C) {
+                float fv[C];
+                load_run<C>(fv, cl.f, (tid + q * T) * 4, x0, RS);
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const int x = x0 + i;
+                    const float v = -fv[i] * z[q][x].x;
+                    if (x < NR) acc[q][x] = v;
+                    else lslot(q, x) = v;
+                }
             }
     } else {
 #pragma unroll
@@ -265,13 +303,19 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
             }
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+    for (int q = 0; q < Q; ++q) {
+        const int v = (tid + q * T) * 4;
+        if (dt == 0.f) {
 #pragma unroll
-        for (int x = 0; x < N; ++x) {
-            const int v = (tid + q * T) * 4;
-            const float a = x < NR ? acc[q][x] : lslot(q, x);
-            bstore(dt == 0.f ? a : __builtin_fmaf(dt, a, bload(cl.f, v, x * RS)), cl.q, v, x * RS);
+            for (int x = 0; x < N; ++x) bstore(x < NR ? acc[q][x] : lslot(q, x), cl.q, v, x * RS);
+        } else {
+            float fv[N];
+            load_run<N>(fv, cl.f, v, 0, RS);
+#pragma unroll
+            for (int x = 0; x < N; ++x)
+                bstore(__builtin_fmaf(dt, x < NR ? acc[q][x] : lslot(q, x), fv[x]), cl.q, v, x * RS);
         }
+    }
 }
 
 
@@ -404,7 +448,7 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
         float2 tg[Q][N];
-        job3d_multiply<N, T, Q>(tg, rgh, pl, J, jb, atab, tid);
+        job3d_multiply<N, T, Q, (chunk3<N, Q>() == 4 ? 4 : 8)>(tg, rgh, pl, J, jb, atab, tid);
         inv3d<N, T, Q, RV>(tg, xb, tid);         // line(g) + i plane(g)
         if constexpr (STAGE) {
 #pragma unroll
@@ -412,7 +456,7 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
 #pragma unroll
                 for (int x = 0; x < N; ++x) bstore2(tg[q][x], rtg, (tid + q * T) * 8, x * RS2);
         }
-        job3d_multiply<N, T, Q>(z, cl.fh, pl, J, jb, atab, tid);
+        job3d_multiply<N, T, Q, (chunk3<N, Q>() == 4 ? 4 : 8)>(z, cl.fh, pl, J, jb, atab, tid);
         inv3d<N, T, Q, RV>(z, xb, tid);          // line(f) + i plane(f)
 #pragma unroll
         for (int q = 0; q < Q; ++q)
@@ -424,12 +468,18 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
             }
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+    for (int q = 0; q < Q; ++q) {
+        const int v = (tid + q * T) * 4;
+        if (dt == 0.f) {
 #pragma unroll
-        for (int x = 0; x < N; ++x) {
-            const int v = (tid + q * T) * 4;
-            bstore(dt == 0.f ? acc[q][x] : __builtin_fmaf(dt, acc[q][x], bload(cl.f, v, x * RS)), cl.q, v, x * RS);
+            for (int x = 0; x < N; ++x) bstore(acc[q][x], cl.q, v, x * RS);
+        } else {
+            float fv[N];
+            load_run<N>(fv, cl.f, v, 0, RS);
+#pragma unroll
+            for (int x = 0; x < N; ++x) bstore(__builtin_fmaf(dt, acc[q][x], fv[x]), cl.q, v, x * RS);
         }
+    }
 }
 
 // um[q][r] = z of the mirror pencil (-Kx, -Ky) at element (n - r) mod n, i.e.
@@ -526,12 +576,17 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         inv3d<N, T, Q, RV>(z, xb, tid);
         // -c l - C(cf) goes to grad_f now and is completed after the direction
         // loop, so that no pencil-sized accumulator stays live through it
+        constexpr int C = N % 8 == 0 ? 8 : N;
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int x = 0; x < N; ++x) {
+            for (int x0 = 0; x0 < N; x0 += C) {
                 const int v = (tid + q * T) * 4;
-                bstore(-bload(rc, v, x * RS) * z[q][x].x - z[q][x].y, cl.q, v, x * RS);
+                float cv[C];
+                load_run<C>(cv, rc, v, x0, RS);
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    bstore(-cv[i] * z[q][x0 + i].x - z[q][x0 + i].y, cl.q, v, (x0 + i) * RS);
             }
     } else {
 #pragma unroll
@@ -620,12 +675,16 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
             for (int k = 0; k < N; ++k) z[q][k] = sh.get(k);
         }
         inv3d<N, T, Q, RV>(z, xb, tid);
+        constexpr int C = N % 8 == 0 ? 8 : N;
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int x = 0; x < N; ++x) {
+            for (int x0 = 0; x0 < N; x0 += C) {
                 const int v = (tid + q * T) * 4;
-                bstore(bload(cl.q, v, x * RS) + z[q][x].x, cl.q, v, x * RS);
+                float gv[C];
+                load_run<C>(gv, cl.q, v, x0, RS);
+#pragma unroll
+                for (int i = 0; i < C; ++i) bstore(gv[i] + z[q][x0 + i].x, cl.q, v, (x0 + i) * RS);
             }
     }
 }

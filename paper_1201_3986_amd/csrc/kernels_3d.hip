@@ -251,7 +251,10 @@ template <int N, int T = t3d<N>()>
 size_t lds3d(int ntilde)
 {
     const size_t tail = std::max<size_t>(2 * (5 * ((T + 63) / 64) + N), (size_t)lacc3d<N, T>() * T);
-    return sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)2 * (ntilde + 1) * N + tail);
+    const size_t bytes = sizeof(float) * ((size_t)N * N * (N + 1) + (size_t)2 * (ntilde + 1) * N + tail);
+    // nine-wave workgroups (n = 24) run one per CU: a second resident one
+    // measured slower (the barriers of the two interleave on the SIMDs)
+    return T == 576 ? std::max<size_t>(bytes, 81 * 1024) : bytes;
 }
 
 // Spread each cell's direction loop over G workgroups when the batch leaves

@@ -237,12 +237,22 @@ size_t batched_slot_elems(int family)
     return family == BF_256 ? (size_t)8 * 32 * 32 : (family == BF_576 ? (size_t)24 * 24 * 24 : (size_t)32 * 32 * 32);
 }
 
+bool batch_uses_counter(const BatchDev& b)
+{
+    for (int c = 0; c < kNumClasses; ++c)
+        if (b.cls_count[c] > 0 && !b.cls_static[c]) return true;
+    return false;
+}
+
 hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, const float* f, float* q, float dt,
                           hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, b.counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // the queue counters are only read by classes whose tickets are dynamic
+    if (batch_uses_counter(b)) {
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, b.counter);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     switch (family) {
         case BF_256: family_launch<256>(b, li, f, q, dt, st); break;
         case BF_576: family_launch<576>(b, li, f, q, dt, st); break;

@@ -150,6 +150,19 @@ struct HalfSpec {
     }
 };
 
+// Elements k0 .. k0 + C - 1 of the lane's pencil (byte stride S) of buffer r,
+// all issued before any of them is used.  Left alone, the scheduler may wait
+// for each read in turn: it cannot move a read past a store to a buffer it
+// cannot tell apart from this one (a result written in place, a spectrum
+// slot), nor always sees that the reads are independent.
+template <int C>
+__device__ __forceinline__ void load_run(float (&v)[C], rsrc_t r, int voff, int k0, int S)
+{
+#pragma unroll
+    for (int i = 0; i < C; ++i) v[i] = bload(r, voff, (k0 + i) * S);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // A byte offset unchanged, but opaque to the optimiser: a later read of a cell
 // through it is not merged with an earlier read of the same address, which
 // would keep the whole pencil alive in registers in between.

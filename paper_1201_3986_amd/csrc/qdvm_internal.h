@@ -146,6 +146,8 @@ struct BatchDev {
 // dtab_floats must be even (the reduction area after the LDS buffers holds doubles)
 hipError_t batched_launch_info(int family, int nitems, bool split, LaunchInfo& li, size_t dtab_floats);
 size_t batched_slot_elems(int family);
+// true if some class of the launch takes dynamic tickets (then a counter reset kernel runs first)
+bool batch_uses_counter(const BatchDev& b);
 hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, const float* f, float* q, float dt,
                           hipStream_t st);
 
