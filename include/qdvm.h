@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QDVM_ABI_VERSION 2
+#define QDVM_ABI_VERSION 3
 
 typedef enum {
     QDVM_OK = 0,
@@ -55,6 +55,7 @@ typedef enum {
 typedef struct qdvm_plan_s* qdvm_plan_t;   /* opaque, immutable after creation */
 typedef struct qdvm_batch_s* qdvm_batch_t; /* opaque heterogeneous batch (cells of several plans) */
 typedef struct qdvm_graph_s* qdvm_graph_t; /* opaque captured Euler step */
+typedef struct qdvm_adaptive_s* qdvm_adaptive_t; /* opaque adaptive-direction-count batch */
 
 /*
  * Plan descriptor: the parameters of Sec. 3.3 (n, the truncation Nt through
@@ -210,6 +211,37 @@ qdvm_status qdvm_step_graph_create_scheme(qdvm_batch_t batch, float* f, float dt
                                           hipStream_t capture_stream, qdvm_graph_t* out);
 qdvm_status qdvm_step_graph_launch(qdvm_graph_t graph, hipStream_t stream);
 qdvm_status qdvm_step_graph_destroy(qdvm_graph_t graph);   /* synchronises the device first; NULL is a no-op */
+
+/*
+ * Adaptive direction count (Sec. 3.3, the remark after the complexity count:
+ * the number of directions may depend on the position, fewer where the
+ * distribution is close to equilibrium).  An adaptive batch evaluates cells of
+ * one grid size, each with the plan of its level.  The level of a cell is the
+ * number of thresholds exceeded by its distance from equilibrium
+ *     r = sum_i |f_i - M_i| / sum_i |f_i|        (r = 0 for a zero cell),
+ * M the Maxwellian of the cell's moments on the index grid (mass s0, mean mu,
+ * temperature var = (sum |i|^2 f / s0 - |mu|^2) / d, as in the
+ * near-equilibrium mode; M = 0 when s0 <= 0 or var <= 1/4), computed in FP64
+ * on the device at every evaluation.
+ *   cell_offset: host, ncells element offsets (as for qdvm_batch_plan).
+ *   level_plan:  host, nlevels (1..8) plans of one dim and n in the batched
+ *                set, either mode, on the current device; borrowed (they must
+ *                outlive the adaptive batch).  List them by increasing cost
+ *                (fewest directions first): the launch drains the last first.
+ *   threshold:   host, nlevels - 1 finite, strictly increasing values.
+ * Errors: EINVAL (null or inconsistent arguments), EUNSUPPORTED (a grid outside
+ * the batched set), ENOMEM / EDEVICE.
+ */
+qdvm_status qdvm_adaptive_plan(int32_t ncells, const int64_t* cell_offset, int32_t nlevels,
+                               const qdvm_plan_t* level_plan, const float* threshold, qdvm_adaptive_t* out);
+/* q = Q(f) (dt == 0) or f + dt Q(f) per cell with its level's directions; q may
+ * equal f.  level (int32) and dist (float) are optional device outputs of
+ * ncells entries (each cell's level and r).  Three launches on the stream: a
+ * counter reset, the classifier (one workgroup per cell) and the persistent
+ * drain of the level queues; nothing is allocated. */
+qdvm_status qdvm_adaptive_eval(qdvm_adaptive_t adaptive, const float* f, float* q, float dt, int32_t* level,
+                               float* dist, hipStream_t stream);
+qdvm_status qdvm_adaptive_destroy(qdvm_adaptive_t adaptive);   /* synchronises the device first; NULL is a no-op */
 
 /* Kernel variant (FFT radix order) used by eval (op 0) and vjp (op 1):
  * -1 restores the built-in default (4 x 8 pencils for 3D n = 32, else

@@ -17,4 +17,6 @@ from .oracle import (  # noqa: F401
     set_num_threads,
     index_maxwellian,
     collide_near_equilibrium,
+    equilibrium_distance,
+    adaptive_levels,
 )

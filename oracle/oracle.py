@@ -196,6 +196,32 @@ def index_maxwellian(d: int, n: int, f) -> np.ndarray:
     return out.reshape(np.shape(f))
 
 
+def equilibrium_distance(d: int, n: int, f) -> np.ndarray:
+    """Distance of each cell from equilibrium, FP64: r = sum |f - M| / sum |f|
+    with M = index_maxwellian(f), and r = 0 for a cell that is zero.
+
+    The measure by which the adaptive batch gives cells close to equilibrium
+    fewer directions (the adaptivity remark of Sec. 3.3 names the criterion,
+    closeness to equilibrium, but no formula; this relative L1 distance is the
+    reading taken).  Returns one value per cell.
+    """
+    flat, batch = _cells(f, d, n)
+    cells = flat.reshape(batch, n ** d)
+    M = index_maxwellian(d, n, cells.reshape((batch,) + (n,) * d)).reshape(batch, n ** d)
+    num = np.abs(cells - M).sum(axis=1)
+    den = np.abs(cells).sum(axis=1)
+    return np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+
+
+def adaptive_levels(r, thresholds) -> np.ndarray:
+    """Level of each cell: how many of the increasing thresholds its distance
+    exceeds (strictly).  The thresholds are compared as given (FP32 values
+    promoted to FP64)."""
+    t = np.asarray(thresholds, dtype=np.float32).astype(np.float64)
+    r = np.asarray(r, dtype=np.float64)
+    return np.array([int(np.sum(x > t)) for x in np.ravel(r)], dtype=np.int32)
+
+
 def collide_near_equilibrium(d, n, ntilde, dirs, w, f) -> np.ndarray:
     """Q(f, f) - Q(M, M) with M = index_maxwellian(f), both by direct summation."""
     M = index_maxwellian(d, n, f)

@@ -47,6 +47,20 @@ struct qdvm_batch_s {
     std::mutex mu;
 };
 
+struct qdvm_adaptive_s {
+    int device = 0;
+    int32_t ncells = 0, nlevels = 0;
+    int64_t* d_cell_in = nullptr;
+    int64_t* d_queue = nullptr;
+    int32_t* d_count = nullptr;
+    float* d_thr = nullptr;
+    qdvm::DevPlan* d_plans = nullptr;
+    float2* d_spec = nullptr;
+    qdvm::LaunchInfo li;
+    qdvm::AdaptDev dev{};
+    std::mutex mu;
+};
+
 struct qdvm_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -818,6 +832,137 @@ const char* qdvm_status_string(qdvm_status s)
 }
 
 const char* qdvm_last_error(void) { return g_last_error.c_str(); }
+
+namespace {
+
+void free_adaptive(qdvm_adaptive_s* a)
+{
+    if (a->d_cell_in) (void)hipFree(a->d_cell_in);
+    if (a->d_queue) (void)hipFree(a->d_queue);
+    if (a->d_count) (void)hipFree(a->d_count);
+    if (a->d_thr) (void)hipFree(a->d_thr);
+    if (a->d_plans) (void)hipFree(a->d_plans);
+    if (a->d_spec) (void)hipFree(a->d_spec);
+}
+
+}  // namespace
+
+qdvm_status qdvm_adaptive_plan(int32_t ncells, const int64_t* cell_offset, int32_t nlevels,
+                               const qdvm_plan_t* level_plan, const float* threshold, qdvm_adaptive_t* out)
+{
+    g_last_error.clear();
+    if (!out) return fail(QDVM_EINVAL, "null output pointer");
+    if (ncells < 1) return fail(QDVM_EINVAL, "ncells must be positive");
+    if (!cell_offset || !level_plan) return fail(QDVM_EINVAL, "null cell_offset or level_plan");
+    if (nlevels < 1 || nlevels > qdvm::kMaxLevels) return fail(QDVM_EINVAL, "nlevels must be in 1..8");
+    if (nlevels > 1 && !threshold) return fail(QDVM_EINVAL, "null threshold");
+    for (int32_t l = 0; l + 1 < nlevels; ++l) {
+        if (!std::isfinite(threshold[l])) return fail(QDVM_EINVAL, "thresholds must be finite");
+        if (l > 0 && !(threshold[l] > threshold[l - 1]))
+            return fail(QDVM_EINVAL, "thresholds must be strictly increasing");
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e, "hipGetDevice");
+    size_t dtab_floats = 0;
+    bool any_split = false;
+    for (int32_t l = 0; l < nlevels; ++l) {
+        const qdvm_plan_s* p = level_plan[l];
+        if (!p) return fail(QDVM_EINVAL, "null plan for level " + std::to_string(l));
+        if (p->hp.device != dev) return fail(QDVM_EINVAL, "a plan belongs to another device than the current one");
+        if (p->hp.dim != level_plan[0]->hp.dim || p->hp.n != level_plan[0]->hp.n)
+            return fail(QDVM_EINVAL, "the level plans must share dim and n");
+        any_split = any_split || p->hp.mode == QDVM_MODE_NEAR_EQUILIBRIUM;
+        dtab_floats = std::max<size_t>(dtab_floats, (size_t)2 * (p->hp.ntilde + 1) * p->hp.n);
+    }
+    const int cls = batch_class(level_plan[0]->hp.dim, level_plan[0]->hp.n);
+    if (cls < 0) return fail(QDVM_EUNSUPPORTED, "adaptive batches support 2D n in {8,16,32,64} and 3D n in {24,32}");
+    const int64_t npts = level_plan[0]->hp.npts();
+    int64_t max_end = 0;
+    for (int32_t c = 0; c < ncells; ++c) {
+        if (cell_offset[c] < 0) return fail(QDVM_EINVAL, "negative cell offset");
+        max_end = std::max<int64_t>(max_end, cell_offset[c] + npts);
+    }
+    if (max_end * 4 >= (int64_t(1) << 31)) return fail(QDVM_EINVAL, "f extent must stay below 2 GiB per batch");
+    qdvm_adaptive_s* a = new (std::nothrow) qdvm_adaptive_s();
+    if (!a) return fail(QDVM_ENOMEM, "host allocation failed");
+    a->device = dev;
+    a->ncells = ncells;
+    a->nlevels = nlevels;
+    dtab_floats = (dtab_floats + 1) & ~size_t(1);
+    e = qdvm::adaptive_launch_info(cls, ncells, any_split, a->li, dtab_floats);
+    if (e != hipSuccess || a->li.grid <= 0) {
+        delete a;
+        return from_hip(e == hipSuccess ? hipErrorInvalidValue : e, "configuring the adaptive kernel");
+    }
+    std::vector<qdvm::DevPlan> plans;
+    for (int32_t l = 0; l < nlevels; ++l) plans.push_back(level_plan[l]->hp.dev());
+    const size_t base_slot = qdvm::batched_slot_elems(class_family(cls));
+    const size_t slot_elems = any_split ? 3 * base_slot : base_slot;   // f, g and staging spectra
+    e = hipMalloc(&a->d_cell_in, sizeof(int64_t) * ncells);
+    if (e == hipSuccess) e = hipMemcpy(a->d_cell_in, cell_offset, sizeof(int64_t) * ncells, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&a->d_queue, sizeof(int64_t) * (size_t)nlevels * ncells);
+    if (e == hipSuccess) e = hipMalloc(&a->d_count, sizeof(int32_t) * qdvm::kMaxLevels);
+    if (e == hipSuccess) e = hipMalloc(&a->d_thr, sizeof(float) * qdvm::kMaxLevels);
+    if (e == hipSuccess && nlevels > 1)
+        e = hipMemcpy(a->d_thr, threshold, sizeof(float) * (nlevels - 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&a->d_plans, sizeof(qdvm::DevPlan) * nlevels);
+    if (e == hipSuccess) e = hipMemcpy(a->d_plans, plans.data(), sizeof(qdvm::DevPlan) * nlevels, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&a->d_spec, sizeof(float2) * slot_elems * a->li.grid);
+    if (e != hipSuccess) {
+        free_adaptive(a);
+        delete a;
+        return from_hip(e, "allocating the adaptive batch tables");
+    }
+    qdvm::AdaptDev& d = a->dev;
+    d.b.plans = a->d_plans;
+    d.b.cell_off = a->d_queue;
+    d.b.spec = a->d_spec;
+    d.b.slot_elems = (int64_t)slot_elems;
+    d.b.gslot = any_split ? (int64_t)base_slot : 0;
+    d.b.fbytes = (uint32_t)(max_end * 4);
+    d.b.dtab_floats = (int32_t)dtab_floats;
+    d.cell_in = a->d_cell_in;
+    d.queue = a->d_queue;
+    d.count = a->d_count;
+    d.thr = a->d_thr;
+    d.nlevels = nlevels;
+    d.ncells = ncells;
+    d.cls = cls;
+    d.cpi = class_cells_per_item(cls);
+    *out = a;
+    return QDVM_OK;
+}
+
+qdvm_status qdvm_adaptive_eval(qdvm_adaptive_t a, const float* f, float* q, float dt, int32_t* level, float* dist,
+                               hipStream_t st)
+{
+    if (!a) return fail(QDVM_EINVAL, "null adaptive batch");
+    if (!f || !q) return fail(QDVM_EINVAL, "null f or q");
+    if (!std::isfinite(dt)) return fail(QDVM_EINVAL, "dt must be finite");
+    std::lock_guard<std::mutex> lock(a->mu);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e, "hipGetDevice");
+    if (dev != a->device) return fail(QDVM_EINVAL, "adaptive batch belongs to another device than the current one");
+    qdvm::AdaptDev d = a->dev;
+    d.level = level;
+    d.dist = dist;
+    e = qdvm::launch_adaptive(d, a->li, f, q, dt, st);
+    if (e != hipSuccess) return from_hip(e, "launching the adaptive kernels");
+    return QDVM_OK;
+}
+
+qdvm_status qdvm_adaptive_destroy(qdvm_adaptive_t a)
+{
+    if (!a) return QDVM_OK;
+    qdvm_status st = QDVM_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) st = from_hip(e, "synchronising before destroying the adaptive batch");
+    free_adaptive(a);
+    delete a;
+    return st;
+}
 
 int32_t qdvm_abi_version(void) { return QDVM_ABI_VERSION; }
 

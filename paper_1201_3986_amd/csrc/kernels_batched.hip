@@ -262,4 +262,170 @@ hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, c
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------- adaptive direction count
+// Sec. 3.3 (remark after the complexity count): the number of directions may
+// depend on the position, with fewer where the distribution is close to
+// equilibrium.  The distance of a cell from equilibrium is the relative L1
+// distance r = sum |f - M| / sum |f| to its Maxwellian M (the index-grid
+// Maxwellian of its moments, FP64, as in the near-equilibrium mode; M = 0 when
+// the cell has none, and r = 0 for a cell that is zero).
+
+namespace {
+
+__global__ void k_adapt_reset(int32_t* count)
+{
+    if (threadIdx.x < kMaxLevels) count[threadIdx.x] = 0;
+}
+
+// One workgroup per cell: moments, the Maxwellian, r, the level, and the
+// cell's place in its level's queue.
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_adapt_classify(AdaptDev a, const float* __restrict__ f)
+{
+    constexpr int NP = D == 2 ? N * N : N * N * N;
+    __shared__ double red[5 * 4];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const float* fc = f + a.cell_in[c];
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // mass, first moments (3), second moment
+    for (int e = tid; e < NP; e += 256) {
+        const int i0 = D == 2 ? e / N : e / (N * N), i1 = D == 2 ? e % N : (e / N) % N, i2 = D == 2 ? 0 : e % N;
+        const double v = fc[e];
+        s[0] += v;
+        s[1] += i0 * v;
+        s[2] += i1 * v;
+        s[3] += i2 * v;
+        s[4] += (double)(i0 * i0 + i1 * i1 + i2 * i2) * v;
+    }
+    block_sum5d<256>(s, red, tid);
+    const double m0 = s[1] / s[0], m1 = s[2] / s[0], m2 = s[3] / s[0];
+    const double var = (s[4] / s[0] - m0 * m0 - m1 * m1 - m2 * m2) / D;
+    const bool ok = s[0] > 0.0 && var > 0.25 && __builtin_isfinite(var) && __builtin_isfinite(m0) &&
+                    __builtin_isfinite(m1) && __builtin_isfinite(m2);
+    const double norm = ok ? s[0] * pow(2.0 * kPi * var, -0.5 * D) : 0.0;
+    const double inv2v = ok ? 0.5 / var : 0.0;
+    double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum |f - M|, sum |f|
+    for (int e = tid; e < NP; e += 256) {
+        const int i0 = D == 2 ? e / N : e / (N * N), i1 = D == 2 ? e % N : (e / N) % N, i2 = D == 2 ? 0 : e % N;
+        const double v = fc[e];
+        const double r2 = (i0 - m0) * (i0 - m0) + (i1 - m1) * (i1 - m1) + (D == 3 ? (i2 - m2) * (i2 - m2) : 0.0);
+        const double M = ok ? norm * exp(-r2 * inv2v) : 0.0;
+        t[0] += fabs(v - M);
+        t[1] += fabs(v);
+    }
+    block_sum5d<256>(t, red, tid);
+    if (tid == 0) {
+        const double r = t[1] > 0.0 ? t[0] / t[1] : 0.0;
+        int lv = 0;
+        for (int l = 0; l + 1 < a.nlevels; ++l)
+            if (r > (double)a.thr[l]) lv = l + 1;
+        if (a.level) a.level[c] = lv;
+        if (a.dist) a.dist[c] = (float)r;
+        const int pos = atomicAdd(a.count + lv, 1);
+        a.queue[(int64_t)lv * a.ncells + pos] = a.cell_in[c];
+    }
+}
+
+// Persistent drain of the level queues of class C (one item: up to cpi cells
+// of one level).  Items are numbered from the last level (the most
+// directions) down and assigned statically; results do not depend on which
+// cells share an item (each cell runs on its own lanes or workgroup).  SPLIT:
+// some level plans are near-equilibrium plans (as for k_batched).
+template <int C, int T, bool SPLIT>
+__global__ __launch_bounds__(T) void k_adaptive(AdaptDev a, const float* f, float* q, float dt)
+{
+    extern __shared__ float smem[];
+    float* dtab = smem;
+    float* xbase = smem + a.b.dtab_floats;
+    double* red = (double*)(xbase + batched_xb_floats(T));
+    float2* slot = a.b.spec + (size_t)blockIdx.x * a.b.slot_elems;
+    const int cpi = a.cpi, nl = uni(a.nlevels);
+    int total = 0;
+    for (int l = 0; l < nl; ++l) total += (uni(a.count[l]) + cpi - 1) / cpi;
+    int cur_plan = -1;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int l = nl - 1, k = t, cnt = uni(a.count[l]);
+        while (k >= (cnt + cpi - 1) / cpi) {
+            k -= (cnt + cpi - 1) / cpi;
+            --l;
+            cnt = uni(a.count[l]);
+        }
+        const BatchItem I = {C, l, l * a.ncells + k * cpi, cnt - k * cpi < cpi ? cnt - k * cpi : cpi};
+        const DevPlan pl = uniform_plan(a.b.plans[l]);
+        if (l != cur_plan) {
+            __syncthreads();                  // the previous item no longer reads the table
+            load_dtab(dtab, pl, threadIdx.x, T);
+            __syncthreads();
+            cur_plan = l;
+        }
+        if constexpr (C == BC_2D8) batch_item_2d<8, T, SPLIT>(pl, I, a.b, f, q, dt, xbase, dtab, slot);
+        else if constexpr (C == BC_2D16) batch_item_2d<16, T, SPLIT>(pl, I, a.b, f, q, dt, xbase, dtab, slot);
+        else if constexpr (C == BC_2D32) batch_item_2d<32, T, SPLIT>(pl, I, a.b, f, q, dt, xbase, dtab, slot);
+        else if constexpr (C == BC_2D64) batch_item_2d<64, T, SPLIT>(pl, I, a.b, f, q, dt, xbase, dtab, slot);
+        else if constexpr (C == BC_3D24) batch_item_3d<24, T, SPLIT>(pl, I, a.b, f, q, dt, xbase, dtab, slot, red);
+        else batch_item_3d<32, T, SPLIT>(pl, I, a.b, f, q, dt, xbase, dtab, slot, red);
+        __syncthreads();                      // LDS free for the next item
+    }
+}
+
+template <int C, int T>
+hipError_t adaptive_info_t(int ncells, bool split, LaunchInfo& li, size_t dtab_floats)
+{
+    li.block = T;
+    li.lds = sizeof(float) * (dtab_floats + batched_xb_floats(T) + kRedFloats + 4);
+    if (T == 576) li.lds = std::max<size_t>(li.lds, 81 * 1024);   // one nine-wave workgroup per CU
+    hipError_t e = split ? occupancy_grid(k_adaptive<C, T, true>, T, li.lds, ncells, li.grid)
+                         : occupancy_grid(k_adaptive<C, T, false>, T, li.lds, ncells, li.grid);
+    li.slots = li.grid;
+    return e;
+}
+
+template <int C, int T>
+void adaptive_drain(const AdaptDev& a, const LaunchInfo& li, const float* f, float* q, float dt, hipStream_t st)
+{
+    if (a.b.gslot != 0) hipLaunchKernelGGL((k_adaptive<C, T, true>), dim3(li.grid), dim3(T), li.lds, st, a, f, q, dt);
+    else hipLaunchKernelGGL((k_adaptive<C, T, false>), dim3(li.grid), dim3(T), li.lds, st, a, f, q, dt);
+}
+
+}  // namespace
+
+hipError_t adaptive_launch_info(int cls, int ncells, bool split, LaunchInfo& li, size_t dtab_floats)
+{
+    switch (cls) {
+        case BC_2D8: return adaptive_info_t<BC_2D8, 256>(ncells, split, li, dtab_floats);
+        case BC_2D16: return adaptive_info_t<BC_2D16, 256>(ncells, split, li, dtab_floats);
+        case BC_2D32: return adaptive_info_t<BC_2D32, 256>(ncells, split, li, dtab_floats);
+        case BC_2D64: return adaptive_info_t<BC_2D64, 512>(ncells, split, li, dtab_floats);
+        case BC_3D24: return adaptive_info_t<BC_3D24, 576>(ncells, split, li, dtab_floats);
+        case BC_3D32: return adaptive_info_t<BC_3D32, 512>(ncells, split, li, dtab_floats);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adaptive(const AdaptDev& a, const LaunchInfo& li, const float* f, float* q, float dt,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adapt_reset, dim3(1), dim3(64), 0, st, a.count);
+    switch (a.cls) {
+        case BC_2D8: hipLaunchKernelGGL((k_adapt_classify<2, 8>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
+        case BC_2D16: hipLaunchKernelGGL((k_adapt_classify<2, 16>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
+        case BC_2D32: hipLaunchKernelGGL((k_adapt_classify<2, 32>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
+        case BC_2D64: hipLaunchKernelGGL((k_adapt_classify<2, 64>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
+        case BC_3D24: hipLaunchKernelGGL((k_adapt_classify<3, 24>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
+        case BC_3D32: hipLaunchKernelGGL((k_adapt_classify<3, 32>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (a.cls) {
+        case BC_2D8: adaptive_drain<BC_2D8, 256>(a, li, f, q, dt, st); break;
+        case BC_2D16: adaptive_drain<BC_2D16, 256>(a, li, f, q, dt, st); break;
+        case BC_2D32: adaptive_drain<BC_2D32, 256>(a, li, f, q, dt, st); break;
+        case BC_2D64: adaptive_drain<BC_2D64, 512>(a, li, f, q, dt, st); break;
+        case BC_3D24: adaptive_drain<BC_3D24, 576>(a, li, f, q, dt, st); break;
+        case BC_3D32: adaptive_drain<BC_3D32, 512>(a, li, f, q, dt, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace qdvm

@@ -146,6 +146,27 @@ struct BatchDev {
 // dtab_floats must be even (the reduction area after the LDS buffers holds doubles)
 hipError_t batched_launch_info(int family, int nitems, bool split, LaunchInfo& li, size_t dtab_floats);
 size_t batched_slot_elems(int family);
+// ------------------------------------------------------------- adaptive direction count
+// Cells of one class, each evaluated with the plan of its level: level l when
+// the cell's distance from its Maxwellian exceeds l of the increasing
+// thresholds (few directions near equilibrium).  The classifier fills one
+// queue of cell offsets per level; the persistent launch drains them.
+constexpr int kMaxLevels = 8;
+struct AdaptDev {
+    BatchDev b;                // plans: one per level; cell_off = queue; gslot != 0 when some level
+                               // plan is a near-equilibrium plan; items, counter unused
+    const int64_t* cell_in;    // [ncells] element offset of each cell, caller's order
+    int64_t* queue;            // [nlevels][ncells] offsets of the cells of each level
+    int32_t* count;            // [kMaxLevels] cells per level
+    int32_t* level;            // [ncells] level of each cell (may be null)
+    float* dist;               // [ncells] distance of each cell from its Maxwellian (may be null)
+    const float* thr;          // [nlevels - 1] thresholds, increasing
+    int32_t nlevels, ncells, cls, cpi;
+};
+hipError_t adaptive_launch_info(int cls, int ncells, bool split, LaunchInfo& li, size_t dtab_floats);
+hipError_t launch_adaptive(const AdaptDev& a, const LaunchInfo& li, const float* f, float* q, float dt,
+                           hipStream_t st);
+
 // true if some class of the launch takes dynamic tickets (then a counter reset kernel runs first)
 bool batch_uses_counter(const BatchDev& b);
 hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, const float* f, float* q, float dt,

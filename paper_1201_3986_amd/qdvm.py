@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libqdvm.so")
 
 QDVM_OK, QDVM_EINVAL, QDVM_EUNSUPPORTED, QDVM_ENOMEM, QDVM_EDEVICE = 0, -1, -2, -3, -4
 MODE_FULL, MODE_NEAR_EQUILIBRIUM = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 _MODES = {"full": MODE_FULL, "near_equilibrium": MODE_NEAR_EQUILIBRIUM}
 
 _lock = threading.Lock()
@@ -75,6 +75,10 @@ def load():
             "qdvm_step_graph_create_scheme": [vp, vp, ctypes.c_float, i32, vp, ctypes.POINTER(vp)],
             "qdvm_step_graph_launch": [vp, vp],
             "qdvm_step_graph_destroy": [vp],
+            "qdvm_adaptive_plan": [i32, ctypes.POINTER(ctypes.c_int64), i32, ctypes.POINTER(vp),
+                                   ctypes.POINTER(ctypes.c_float), ctypes.POINTER(vp)],
+            "qdvm_adaptive_eval": [vp, vp, vp, ctypes.c_float, vp, vp, vp],
+            "qdvm_adaptive_destroy": [vp],
         }
         for name, args in sigs.items():
             fn = getattr(lib, name)
@@ -296,6 +300,52 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+class AdaptivePlan(BatchPlan):
+    """Cells of one grid size, each evaluated with the plan of its level:
+    level l when the cell's distance from its Maxwellian, sum|f - M| / sum|f|,
+    exceeds l of the increasing `thresholds` (len(level_plans) - 1 values).
+    The levels are chosen on the device at every evaluation."""
+
+    def __init__(self, level_plans, offsets, thresholds):
+        lib = load()
+        self._plans = list(level_plans)      # plans must outlive the batch
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float32))
+        if len(thr) != max(len(self._plans) - 1, 0):
+            raise ValueError("need len(level_plans) - 1 thresholds")
+        self.thresholds = thr
+        npts = self._plans[0].npts if self._plans else 0
+        self.npts = npts
+        self.extent = int(self.offsets.max() + npts) if len(self.offsets) else 0
+        h = ctypes.c_void_p()
+        _check(lib.qdvm_adaptive_plan(len(self.offsets), self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      len(self._plans), _plan_array(self._plans),
+                                      thr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(h)))
+        self._h = h
+
+    def eval(self, f, out=None, dt=0.0, levels=False, stream=None):
+        """Q per cell (or f + dt Q); with levels=True also returns each cell's
+        level (int32) and distance from equilibrium (float32) as CUDA tensors."""
+        import torch
+        self._check_buf(f, "f")
+        if out is None:
+            out = torch.empty_like(f)
+        self._check_buf(out, "out")
+        lv = dist = None
+        if levels:
+            lv = torch.empty(len(self.offsets), dtype=torch.int32, device=f.device)
+            dist = torch.empty(len(self.offsets), dtype=torch.float32, device=f.device)
+        _check(load().qdvm_adaptive_eval(self._h, _ptr(f), _ptr(out), float(dt),
+                                         _ptr(lv) if levels else None, _ptr(dist) if levels else None,
+                                         _stream_ptr(stream)))
+        return (out, lv, dist) if levels else out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().qdvm_adaptive_destroy(self._h))
+            self._h = ctypes.c_void_p()
 
 
 STEP_EULER, STEP_RK2 = 0, 1

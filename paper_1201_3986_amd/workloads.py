@@ -151,3 +151,25 @@ def three_gaussians_batch(seed: int, cells: int, n: int, R: float = 8.0) -> np.n
     """`cells` independent draws of the c3 family, shape (cells, n, n, n), float32."""
     rng = np.random.default_rng(seed)
     return np.stack([_three_gaussians(rng, 3, n, R) for _ in range(cells)]).astype(np.float32)
+
+
+def relaxation_mix(seed: int, cells: int, d: int, n: int, R: float = 8.0) -> tuple:
+    """Spatially inhomogeneous cells at several distances from equilibrium, in
+    the order kind = c % 4: a local Maxwellian times (1 + a U[-1,1]) with
+    a = 0.002, 0.03 and 0.15, then two unit-mass Maxwellians (T ~ U[0.5, 1.5])
+    centred at +-s u, s ~ U[1.5, 2], u a random unit vector (well separated,
+    far from equilibrium).  Returns (f of shape (cells,) + (n,) * d, float32;
+    kind per cell)."""
+    rng = np.random.default_rng(seed)
+    out, kind = [], []
+    for c in range(cells):
+        k = c % 4
+        if k < 3:
+            out.append(noisy_local_maxwellian(rng, d, n, R, (0.002, 0.03, 0.15)[k]))
+        else:
+            u = rng.standard_normal(d)
+            u *= rng.uniform(1.5, 2.0) / np.linalg.norm(u)
+            out.append(maxwellian(d, n, R, 1.0, u, rng.uniform(0.5, 1.5))
+                       + maxwellian(d, n, R, 1.0, -u, rng.uniform(0.5, 1.5)))
+        kind.append(k)
+    return np.stack(out).astype(np.float32), np.array(kind, dtype=np.int32)

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
     assert len(names) >= 12
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.qdvm_abi_version() == qdvm.ABI_VERSION == 2
+    assert lib.qdvm_abi_version() == qdvm.ABI_VERSION == 3
 
 
 def test_status_strings():

@@ -1,0 +1,169 @@
+"""GPU adaptive direction count: each cell evaluated with the plan of its
+level, the level chosen on the device from the cell's distance to its
+Maxwellian (oracle.equilibrium_distance, oracle.adaptive_levels).
+
+* the levels equal the oracle's exactly (the inputs keep every distance away
+  from the thresholds, checked in the test) and the distances agree to FP32;
+* each cell equals the single-plan evaluation of its level's plan (bit for bit
+  in 2D, <= 1e-6 of max|Q| in 3D) and the FP64 oracle with that level's
+  directions (<= 1e-5 of max|Q| per cell): near-equilibrium plans against
+  their definition Q(f, f) - Q(M, M) on every sampled cell, full plans on the
+  cells far from equilibrium (near it, plain FP32 cannot resolve Q to 1e-5:
+  the reason for the near-equilibrium mode);
+* empty levels, one level, a zero cell, in-place Euler updates, and argument
+  errors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_3986_amd import workloads
+from parity_util import oracle_q, per_cell_rel_linf, rel_linf
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+THR = np.array([0.004, 0.04], np.float32)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _levels_plans(gpu_lib, d, n, counts, mode="full"):
+    modes = [mode] * len(counts) if isinstance(mode, str) else mode
+    return [gpu_lib.Plan(d, n, 8.0, num_dirs=P, mode=m) for P, m in zip(counts, modes)]
+
+
+def _oracle(plan, f32):
+    if plan.mode == 0:
+        return oracle_q(plan, f32)
+    w = np.float32(plan.weights).astype(np.float64)
+    return oracle.collide_near_equilibrium(plan.dim, plan.n, plan.ntilde, plan.dirs, w,
+                                           np.asarray(f32, np.float32).astype(np.float64))
+
+
+def _run(ad, flat, **kw):
+    import torch
+    out, lv, dist = ad.eval(_dev(flat), levels=True, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), lv.cpu().numpy(), dist.cpu().numpy()
+
+
+def _check_margin(r, thr):
+    # no distance within 10 % of a threshold: the level decision is unambiguous
+    for t in np.float32(thr).astype(np.float64):
+        assert np.min(np.abs(np.log(r / t))) > 0.1
+
+
+@pytest.mark.parametrize("cells,mode", [(64, "near_equilibrium"), (13, "full"),
+                                        (22, ["near_equilibrium", "near_equilibrium", "full"])])
+def test_2d_levels_single_plan_and_oracle(gpu_lib, cells, mode):
+    import torch
+    n, counts = 32, (4, 8, 16)
+    f, kind = workloads.relaxation_mix(21 + cells, cells, 2, n)
+    plans = _levels_plans(gpu_lib, 2, n, counts, mode)
+    offs = np.arange(cells, dtype=np.int64) * n * n
+    ad = gpu_lib.AdaptivePlan(plans, offs, THR)
+    q, lv, dist = _run(ad, f.reshape(-1))
+    r = oracle.equilibrium_distance(2, n, f)
+    _check_margin(r, THR)
+    ref_lv = oracle.adaptive_levels(r, THR)
+    assert np.array_equal(lv, ref_lv)
+    assert np.max(np.abs(dist - r) / r) <= 1e-5
+    assert set(ref_lv.tolist()) == {0, 1, 2}
+    q = q.reshape(cells, -1)
+    for c in range(cells):
+        single = plans[lv[c]].eval(_dev(f[c]))
+        torch.cuda.synchronize()
+        assert np.array_equal(q[c], single.cpu().numpy().reshape(-1)), c
+    checked = 0
+    for c in range(cells):
+        if plans[lv[c]].mode == 0 and kind[c] < 2:
+            continue
+        assert rel_linf(q[c], _oracle(plans[lv[c]], f[c])) <= TOL, (c, lv[c])
+        checked += 1
+        if checked == 12:
+            break
+    assert checked >= 4
+
+
+def test_3d_levels_and_oracle(gpu_lib):
+    import torch
+    n, cells, counts = 24, 8, (4, 8, 13)
+    f, kind = workloads.relaxation_mix(31, cells, 3, n)
+    plans = _levels_plans(gpu_lib, 3, n, counts, "near_equilibrium")
+    offs = np.arange(cells, dtype=np.int64) * n ** 3 + 5 * np.arange(cells)   # gaps between cells
+    flat = np.full(int(offs[-1]) + n ** 3, -3.0, np.float32)
+    for c in range(cells):
+        flat[offs[c]:offs[c] + n ** 3] = f[c].reshape(-1)
+    ad = gpu_lib.AdaptivePlan(plans, offs, THR)
+    q, lv, dist = _run(ad, flat)
+    r = oracle.equilibrium_distance(3, n, f)
+    _check_margin(r, THR)
+    assert np.array_equal(lv, oracle.adaptive_levels(r, THR))
+    assert np.max(np.abs(dist - r) / r) <= 1e-5
+    for c in range(cells):
+        got = q[offs[c]:offs[c] + n ** 3]
+        single = plans[lv[c]].eval(_dev(f[c]))
+        torch.cuda.synchronize()
+        assert rel_linf(got, single.cpu().numpy()) <= 1e-6
+        if c < 4:
+            assert rel_linf(got, _oracle(plans[lv[c]], f[c])) <= TOL, (c, lv[c])
+
+
+def test_one_level_equals_batch_and_empty_levels(gpu_lib):
+    import torch
+    n, cells = 16, 40
+    f = workloads.random_positive(5, 2, n, cells).reshape(cells, -1)   # far from equilibrium: top level only
+    p8 = gpu_lib.Plan(2, n, 8.0, num_dirs=8)
+    offs = np.arange(cells, dtype=np.int64) * n * n
+    flat = f.reshape(-1)
+    single = gpu_lib.AdaptivePlan([p8], offs, [])
+    q1, lv1, _ = _run(single, flat)
+    assert np.all(lv1 == 0)
+    b = gpu_lib.BatchPlan([p8] * cells, offs)
+    qb = b.eval(_dev(flat))
+    torch.cuda.synchronize()
+    assert np.array_equal(q1, qb.cpu().numpy())
+    # three levels, every cell in the last one: the lower queues stay empty
+    three = gpu_lib.AdaptivePlan(_levels_plans(gpu_lib, 2, n, (2, 4)) + [p8], offs, [1e-6, 1e-5])
+    q3, lv3, _ = _run(three, flat)
+    assert np.all(lv3 == 2)
+    assert np.array_equal(q3, q1)
+
+
+def test_zero_cell_and_in_place_euler(gpu_lib):
+    import torch
+    n, cells = 32, 9
+    f, _ = workloads.relaxation_mix(41, cells, 2, n)
+    f[4] = 0.0
+    plans = _levels_plans(gpu_lib, 2, n, (4, 8, 16))
+    offs = np.arange(cells, dtype=np.int64) * n * n
+    ad = gpu_lib.AdaptivePlan(plans, offs, THR)
+    q, lv, dist = _run(ad, f.reshape(-1))
+    assert lv[4] == 0 and dist[4] == 0.0 and np.all(q.reshape(cells, -1)[4] == 0.0)
+    dt = 0.01
+    x = _dev(f.reshape(-1))
+    ad.eval(x, out=x, dt=dt)
+    torch.cuda.synchronize()
+    ref = f.reshape(cells, -1).astype(np.float64) + dt * q.reshape(cells, -1)
+    assert rel_linf(x.cpu().numpy(), ref) <= 1e-6
+
+
+def test_argument_errors(gpu_lib):
+    p16 = gpu_lib.Plan(2, 16, 8.0, num_dirs=8)
+    p32 = gpu_lib.Plan(2, 32, 8.0, num_dirs=8)
+    p3d16 = gpu_lib.Plan(3, 16, 8.0, num_dirs=8)
+    offs = np.zeros(2, np.int64)
+    cases = [
+        (([p16, p32], offs, [0.1]), gpu_lib.QDVM_EINVAL),          # grids differ
+        (([p3d16], offs, []), gpu_lib.QDVM_EUNSUPPORTED),          # 3D n = 16 is not in the batched set
+        (([p16, p16, p16], offs, [0.2, 0.1]), gpu_lib.QDVM_EINVAL),  # thresholds not increasing
+        (([p16, p16], offs, [np.nan]), gpu_lib.QDVM_EINVAL),
+        (([p16], np.array([-4, 0], np.int64), []), gpu_lib.QDVM_EINVAL),
+    ]
+    for args, status in cases:
+        with pytest.raises(gpu_lib.QdvmError) as ei:
+            gpu_lib.AdaptivePlan(*args)
+        assert ei.value.status == status, args
