@@ -158,6 +158,38 @@ def batched_step(qdvm, workloads, torch, args):
     return out
 
 
+def adaptive_step(qdvm, workloads, torch, args):
+    """Adaptive direction count (near-equilibrium plans with P = 4, 8 and 16
+    chosen per cell on the device, thresholds 0.004 and 0.04 of the distance
+    from the cell's Maxwellian) on cells at four distances from equilibrium
+    (workloads.relaxation_mix): 32768 2D n=32 cells and 512 3D n=24 cells,
+    each against the same cells all at P = 16 in one batched launch."""
+    out = {}
+    for d, n, cells, key in ((2, 32, 32768, "adaptive_2d_n32"), (3, 24, 512, "adaptive_3d_n24")):
+        f_np, _ = workloads.relaxation_mix(707 + d, min(cells, 4096), d, n)
+        f_np = np.ascontiguousarray(np.tile(f_np.reshape(len(f_np), -1), (cells // len(f_np), 1)))
+        x = torch.from_numpy(f_np.reshape(-1)).cuda()
+        q = torch.empty_like(x)
+        offs = np.arange(cells, dtype=np.int64) * n ** d
+        plans = [qdvm.Plan(d, n, 8.0, num_dirs=P, mode="near_equilibrium") for P in (4, 8, 16)]
+        ad = qdvm.AdaptivePlan(plans, offs, [0.004, 0.04])
+        _, lv, _ = ad.eval(x, out=q, levels=True)
+        counts = np.bincount(lv.cpu().numpy(), minlength=3)
+        ta = time_calls(lambda: ad.eval(x, out=q), max(5, args.steps // 2), 2)
+        b = qdvm.BatchPlan([plans[2]] * cells, offs)
+        tu = time_calls(lambda: b.eval(x, out=q), max(5, args.steps // 2), 2)
+        log("%s: P in (4, 8, 16), near-equilibrium mode, %d cells (per level %s): %.3f ms; all at P=16 %.3f ms"
+            % (key, cells, counts.tolist(), ta, tu))
+        out[key] = {"ms": ta, "cells_per_s": cells / (ta * 1e-3), "cells_per_level_P4_P8_P16": counts.tolist(),
+                    "uniform_P16_ms": tu, "speedup_vs_uniform_P16": tu / ta}
+        ad.close()
+        b.close()
+        for p in plans:
+            p.close()
+        del x, q
+    return out
+
+
 def profile_workload(args, qdvm, workloads, torch):
     """One secondary workload alone: 3D n=32 P=16 on 2048 cells, its adjoint on
     the 64-cell differentiation batch, or the captured batched Euler step."""
@@ -314,6 +346,7 @@ def main():
         del f3, q3
         torch.cuda.empty_cache()
         results.update(batched_step(qdvm, workloads, torch, args))
+        results.update(adaptive_step(qdvm, workloads, torch, args))
 
     # ---------------------------------------------------------------- CPU oracle
     cpu = None

@@ -277,8 +277,28 @@ __global__ void k_adapt_reset(int32_t* count)
     if (threadIdx.x < kMaxLevels) count[threadIdx.x] = 0;
 }
 
-// One workgroup per cell: moments, the Maxwellian, r, the level, and the
-// cell's place in its level's queue.
+// Level of a cell at distance r (the number of thresholds exceeded); also
+// stores r and the level to the optional outputs.
+__device__ __forceinline__ int adapt_level(const AdaptDev& a, int c, double r)
+{
+    int lv = 0;
+    for (int l = 0; l + 1 < a.nlevels; ++l)
+        if (r > (double)a.thr[l]) lv = l + 1;
+    if (a.level) a.level[c] = lv;
+    if (a.dist) a.dist[c] = (float)r;
+    return lv;
+}
+
+// One cell's place in its level's queue (one atomic per cell).
+__device__ __forceinline__ void adapt_enqueue(const AdaptDev& a, int c, double r)
+{
+    const int lv = adapt_level(a, c, r);
+    const int pos = atomicAdd(a.count + lv, 1);
+    a.queue[(int64_t)lv * a.ncells + pos] = a.cell_in[c];
+}
+
+// 3D cells: one workgroup per cell, two passes over the cell (moments, then
+// the distance from the Maxwellian).
 template <int D, int N>
 __global__ __launch_bounds__(256) void k_adapt_classify(AdaptDev a, const float* __restrict__ f)
 {
@@ -303,25 +323,102 @@ __global__ __launch_bounds__(256) void k_adapt_classify(AdaptDev a, const float*
                     __builtin_isfinite(m1) && __builtin_isfinite(m2);
     const double norm = ok ? s[0] * pow(2.0 * kPi * var, -0.5 * D) : 0.0;
     const double inv2v = ok ? 0.5 / var : 0.0;
+    // M = norm E0(i0) E1(i1) E2(i2), the one-dimensional factors in LDS
+    __shared__ double ex[3][N];
+    if (tid < N) {
+        ex[0][tid] = exp(-(tid - m0) * (tid - m0) * inv2v);
+        ex[1][tid] = exp(-(tid - m1) * (tid - m1) * inv2v);
+        ex[2][tid] = D == 3 ? exp(-(tid - m2) * (tid - m2) * inv2v) : 1.0;
+    }
+    __syncthreads();
     double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum |f - M|, sum |f|
     for (int e = tid; e < NP; e += 256) {
         const int i0 = D == 2 ? e / N : e / (N * N), i1 = D == 2 ? e % N : (e / N) % N, i2 = D == 2 ? 0 : e % N;
         const double v = fc[e];
-        const double r2 = (i0 - m0) * (i0 - m0) + (i1 - m1) * (i1 - m1) + (D == 3 ? (i2 - m2) * (i2 - m2) : 0.0);
-        const double M = ok ? norm * exp(-r2 * inv2v) : 0.0;
+        const double M = ok ? norm * ex[0][i0] * ex[1][i1] * ex[2][i2] : 0.0;
         t[0] += fabs(v - M);
         t[1] += fabs(v);
     }
     block_sum5d<256>(t, red, tid);
-    if (tid == 0) {
-        const double r = t[1] > 0.0 ? t[0] / t[1] : 0.0;
-        int lv = 0;
-        for (int l = 0; l + 1 < a.nlevels; ++l)
-            if (r > (double)a.thr[l]) lv = l + 1;
-        if (a.level) a.level[c] = lv;
-        if (a.dist) a.dist[c] = (float)r;
-        const int pos = atomicAdd(a.count + lv, 1);
-        a.queue[(int64_t)lv * a.ncells + pos] = a.cell_in[c];
+    if (tid == 0) adapt_enqueue(a, c, t[1] > 0.0 ? t[0] / t[1] : 0.0);
+}
+
+// 2D cells: one wave per cell, the cell held in registers (n^2 / 64 values per
+// lane, element e = lane + 64 k), wave-wide sums only.  A workgroup classifies
+// 64 cells and claims their queue places with one atomic per level (per-cell
+// atomics on a few counters serialise).
+template <int N>
+__global__ __launch_bounds__(256) void k_adapt_classify_2d(AdaptDev a, const float* __restrict__ f)
+{
+    constexpr int K = N * N / 64, CPB = 64;
+    __shared__ int s_lv[CPB];
+    __shared__ int s_base[kMaxLevels];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c0 = blockIdx.x * CPB;
+    const int nc = a.ncells - c0 < CPB ? a.ncells - c0 : CPB;
+    for (int j = wave; j < nc; j += 4) {
+        const int c = c0 + j;
+        const float* fc = f + a.cell_in[c];
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = fc[lane + 64 * k];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, sq = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = lane + 64 * k, i0 = e / N, i1 = e % N;
+            const double x = v[k];
+            s0 += x;
+            s1 += i0 * x;
+            s2 += i1 * x;
+            sq += (double)(i0 * i0 + i1 * i1) * x;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            s0 += __shfl_xor(s0, o, 64);
+            s1 += __shfl_xor(s1, o, 64);
+            s2 += __shfl_xor(s2, o, 64);
+            sq += __shfl_xor(sq, o, 64);
+        }
+        const double m0 = s1 / s0, m1 = s2 / s0;
+        const double var = 0.5 * (sq / s0 - m0 * m0 - m1 * m1);
+        const bool ok = s0 > 0.0 && var > 0.25 && __builtin_isfinite(var) && __builtin_isfinite(m0) &&
+                        __builtin_isfinite(m1);
+        const double norm = ok ? s0 / (2.0 * kPi * var) : 0.0;
+        const double inv2v = ok ? 0.5 / var : 0.0;
+        // M(i0, i1) = norm E0(i0) E1(i1): lane l computes E0(l mod n) and
+        // E1(l mod n) (two exps per lane).  i1 = e mod n = l mod n for every k,
+        // so E1 is the lane's own; E0(i0) comes from lane i0 by shuffle.
+        const int li = lane % N;
+        const double e0l = exp(-(li - m0) * (li - m0) * inv2v), e1 = exp(-(li - m1) * (li - m1) * inv2v);
+        double dsum = 0.0, fsum = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = lane + 64 * k, i0 = e / N;
+            const double x = v[k];
+            const double M = ok ? norm * __shfl(e0l, i0, 64) * e1 : 0.0;
+            dsum += fabs(x - M);
+            fsum += fabs(x);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            dsum += __shfl_xor(dsum, o, 64);
+            fsum += __shfl_xor(fsum, o, 64);
+        }
+        if (lane == 0) s_lv[j] = adapt_level(a, c, fsum > 0.0 ? dsum / fsum : 0.0);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < a.nlevels) {
+        int cnt = 0;
+        for (int j = 0; j < nc; ++j) cnt += s_lv[j] == t;
+        s_base[t] = cnt ? atomicAdd(a.count + t, cnt) : 0;
+    }
+    __syncthreads();
+    if (t < nc) {
+        const int lv = s_lv[t];
+        int rank = 0;
+        for (int j = 0; j < t; ++j) rank += s_lv[j] == lv;
+        a.queue[(int64_t)lv * a.ncells + s_base[lv] + rank] = a.cell_in[c0 + t];
     }
 }
 
@@ -405,11 +502,12 @@ hipError_t launch_adaptive(const AdaptDev& a, const LaunchInfo& li, const float*
                            hipStream_t st)
 {
     hipLaunchKernelGGL(k_adapt_reset, dim3(1), dim3(64), 0, st, a.count);
+    const unsigned w4 = (unsigned)((a.ncells + 63) / 64);   // 2D: 64 cells per workgroup
     switch (a.cls) {
-        case BC_2D8: hipLaunchKernelGGL((k_adapt_classify<2, 8>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
-        case BC_2D16: hipLaunchKernelGGL((k_adapt_classify<2, 16>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
-        case BC_2D32: hipLaunchKernelGGL((k_adapt_classify<2, 32>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
-        case BC_2D64: hipLaunchKernelGGL((k_adapt_classify<2, 64>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
+        case BC_2D8: hipLaunchKernelGGL((k_adapt_classify_2d<8>), dim3(w4), dim3(256), 0, st, a, f); break;
+        case BC_2D16: hipLaunchKernelGGL((k_adapt_classify_2d<16>), dim3(w4), dim3(256), 0, st, a, f); break;
+        case BC_2D32: hipLaunchKernelGGL((k_adapt_classify_2d<32>), dim3(w4), dim3(256), 0, st, a, f); break;
+        case BC_2D64: hipLaunchKernelGGL((k_adapt_classify_2d<64>), dim3(w4), dim3(256), 0, st, a, f); break;
         case BC_3D24: hipLaunchKernelGGL((k_adapt_classify<3, 24>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
         case BC_3D32: hipLaunchKernelGGL((k_adapt_classify<3, 32>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
         default: return hipErrorInvalidValue;
