@@ -313,6 +313,14 @@ def main():
         results["2d_n64_P16_near_equilibrium"] = {"cells_per_s": B / (t * 1e-3), "ms": t, "rel_err_vs_Qff": e}
         log("near-equilibrium 2D n=64 P=16: %.3f ms, rel err %.2e" % (t, e))
         pn.close()
+        # 2D adjoint on the headline cells (same f, a N(0,1) cotangent)
+        cot = torch.from_numpy(np.random.default_rng(106).standard_normal(f.shape).astype(np.float32)).cuda()
+        tv = time_calls(lambda: plan.vjp(f, cot), max(5, args.steps // 5), 2)
+        results["vjp_2d_n64_P16"] = {
+            "ms": tv, "eval_ms_same_batch": ms, "vjp_over_eval": tv / ms, "cells_per_s": B / (tv * 1e-3),
+            "tflops": vjp_algorithmic_flops(2, 64, plan.num_jobs) * B / (tv * 1e-3) / 1e12}
+        log("VJP 2D n=64 P=16 %d cells: %.3f ms (eval %.3f ms, ratio %.2f)" % (B, tv, ms, tv / ms))
+        del cot
         del f, q
         torch.cuda.empty_cache()
 

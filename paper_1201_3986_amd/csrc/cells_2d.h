@@ -328,25 +328,36 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
     }
 }
 
-// Adjoint of one 2D cell; the algebra is written out above cell3d_vjp.
+// Adjoint of one 2D cell; the algebra is written out above cell3d_vjp (R, the
+// Hermitian accumulator S).  The mirror row -K0 of the lane's row K0 = j is
+// another lane of the same wave: uhat(-K) comes by shuffle.  rr: the table R
+// (half rows, 4 bytes per element) in the second spectral slot.
 template <int N, int RV>
-__device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, rsrc_t rc, rsrc_t rch,
+__device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, rsrc_t rc, rsrc_t rr,
                                            rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
                                            float* __restrict__ gwp, bool valid, float inv_n2, float inv_n,
                                            float* xb, const float* dtab, int j)
 {
     constexpr int RS = N * 4, RS2 = N * 8;
+    const int mrow = (N - j) & (N - 1);                          // mirror row
+    const int mlane = (int)(threadIdx.x & 63) - j + mrow;        // its lane in the wave
+    const int rown = it.vspec / 2, rmir = rown + (mrow - j) * 4; // R: own and mirror row offsets
     float2 z[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
     fwd2d<N, RV>(z, xb, j);
-    const HalfSpec<N, N * 8> fh = half2d<N>(it.fh, it.vspec, j), ch = half2d<N>(rch, it.vspec, j);
+    const HalfSpec<N, N * 8> fh = half2d<N>(it.fh, it.vspec, j);
     fh.put(z);
 #pragma unroll
     for (int i = 0; i < N; ++i)
         z[i] = make_float2(bload(rc, it.vcell, i * RS) * bload(it.f, it.vcell, i * RS), 0.f);
     fwd2d<N, RV>(z, xb, j);
-    ch.put(z);
+    // R = Re(conj F(cf) fhat) on the own half row (written by this lane)
+#pragma unroll
+    for (int k = 0; k <= N / 2; ++k) {
+        const float2 F = fh.get(k);
+        bstore(__builtin_fmaf(z[k].x, F.x, z[k].y * F.y), rr, rown, k * RS);
+    }
     // IFFT(Lambda (fhat + i F(cf))) = l + i C_Lambda(cf)
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -376,10 +387,10 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const float2 F = fh.get(k);
-                const float2 C = ch.get(k);
+                const float R = k <= N / 2 ? bload(rr, rown, k * RS) : bload(rr, rmir, (N - k) * RS);
                 const float al = a.get(), ap = b.get();
                 z[k] = make_float2(__builtin_fmaf(al, F.x, -ap * F.y), __builtin_fmaf(al, F.y, ap * F.x));
-                spart = __builtin_fmaf(al * ap, __builtin_fmaf(C.x, F.x, C.y * F.y), spart);
+                spart = __builtin_fmaf(al * ap, R, spart);
                 a.next();
                 b.next();
                 QDVM_CHUNK_FENCE(k);
@@ -401,13 +412,19 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
         if (j == 0 && valid) gwp[jb] = tot;
         fwd2d<N, RV>(z, xb, j);
         {
-            RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * j), modc<N>(J.e[1]));
-            RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
+            // the multipliers are read again rather than kept from the first
+            // multiply (holding them through two transforms costs registers)
+            const int jj = reread(j);
+            RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * jj), modc<N>(J.e[1]));
+            RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * jj), modc<N>(J.e[0]));
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const float al = cw * a.get(), ap = cw * b.get();
-                // S += W (alpha - i alpha') Y
-                float2 t = make_float2(__builtin_fmaf(al, z[k].x, ap * z[k].y), __builtin_fmaf(al, z[k].y, -ap * z[k].x));
+            for (int k = 0; k <= N / 2; ++k) {
+                // Hermitian part of (alpha - i alpha') uhat: uhat(-K) is element
+                // n - k of the mirror row
+                const float mx = __shfl(z[(N - k) % N].x, mlane, 64), my = __shfl(z[(N - k) % N].y, mlane, 64);
+                const float al = 0.5f * cw * a.get(), ap = 0.5f * cw * b.get();
+                float2 t = make_float2(__builtin_fmaf(al, z[k].x + mx, ap * (z[k].y + my)),
+                                       __builtin_fmaf(al, z[k].y - my, -ap * (z[k].x - mx)));
                 if (jb > 0) {
                     const float2 sv = bload2(rsh, it.vspec, k * RS2);
                     t.x += sv.x;
@@ -421,8 +438,9 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
         }
     }
     if (pl.njobs > 0) {
+        const HalfSpec<N, N * 8> sh = half2d<N>(rsh, it.vspec, j);
 #pragma unroll
-        for (int k = 0; k < N; ++k) z[k] = bload2(rsh, it.vspec, k * RS2);
+        for (int k = 0; k < N; ++k) z[k] = sh.get(k);
         inv2d<N, RV>(z, xb, j);
         {
             float gv[N];

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const floa
     const float inv_n2 = inv_n * inv_n;
     const size_t sbase = (size_t)blockIdx.x * CPB * NPTS;
     const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
-    const rsrc_t rch = make_rsrc(s.spec2 + sbase, CPB * NPTS * 8);
+    const rsrc_t rr = make_rsrc(s.spec2 + sbase, CPB * NPTS * 8);
     const rsrc_t rsh = make_rsrc(s.acc + sbase, CPB * NPTS * 8);
     Item2D it;
     it.fh = make_rsrc(s.spec + sbase, CPB * NPTS * 8);
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const floa
         it.f = make_rsrc(f + (size_t)first * NPTS, nvalid * NPTS * 4);
         it.q = make_rsrc(g + (size_t)first * NPTS, nvalid * NPTS * 4);
         const rsrc_t rc = make_rsrc(c + (size_t)first * NPTS, nvalid * NPTS * 4);
-        cell2d_vjp<N, RV>(pl, it, rc, rch, rsh, rlam, s.jobw, s.gw_part + (size_t)(valid ? cell : 0) * pl.njobs,
+        cell2d_vjp<N, RV>(pl, it, rc, rr, rsh, rlam, s.jobw, s.gw_part + (size_t)(valid ? cell : 0) * pl.njobs,
                           valid, inv_n2, inv_n, xb, dtab, j);
     }
 }

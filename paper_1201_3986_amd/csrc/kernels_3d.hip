@@ -208,18 +208,25 @@ __global__ void k_prep(DevPlan pl, const float* __restrict__ w, float* __restric
     lam[idx] = (float)(acc * inv);
 }
 
-// grad_w[p] = sum over cells of the job partial of the job holding p (0 if none);
-// fixed summation order over cells, in FP64.
-__global__ void k_gw_reduce(DevPlan pl, int batch, const int32_t* __restrict__ dir_job,
-                            const float* __restrict__ part, float* __restrict__ gw)
+// grad_w[p] = sum over cells of the job partial of the job holding p (0 if none),
+// in FP64: one workgroup per direction, thread t summing cells t, t + 256, ...,
+// then a fixed tree over the threads (the order does not depend on timing).
+__global__ __launch_bounds__(256) void k_gw_reduce(DevPlan pl, int batch, const int32_t* __restrict__ dir_job,
+                                                   const float* __restrict__ part, float* __restrict__ gw)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= pl.P) return;
+    __shared__ double red[256];
+    const int p = blockIdx.x, tid = threadIdx.x;
     const int jb = dir_job[p];
     double acc = 0.0;
     if (jb >= 0)
-        for (int c = 0; c < batch; ++c) acc += (double)part[(size_t)c * pl.njobs + jb];
-    gw[p] = (float)acc;
+        for (int c = tid; c < batch; c += 256) acc += (double)part[(size_t)c * pl.njobs + jb];
+    red[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) gw[p] = (float)red[0];
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -412,8 +419,7 @@ hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float*
     }
     if (e != hipSuccess) return e;
     if (grad_w) {
-        hipLaunchKernelGGL(k_gw_reduce, dim3((pl.P + 63) / 64), dim3(64), 0, st, pl, batch, pl.dir_job,
-                           s.gw_part, grad_w);
+        hipLaunchKernelGGL(k_gw_reduce, dim3(pl.P), dim3(256), 0, st, pl, batch, pl.dir_job, s.gw_part, grad_w);
         e = hipGetLastError();
     }
     return e;
