@@ -376,6 +376,10 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
         for (int i = 0; i < N; ++i) bstore(-cv[i] * z[i].x - z[i].y, it.q, it.vcell, i * RS);
     }
 
+    // the accumulator starts at zero (an unconditional read-modify-write in the
+    // job loop keeps that loop free of per-element branches)
+#pragma unroll
+    for (int k = 0; k <= N / 2; ++k) bstore2(make_float2(0.f, 0.f), rsh, it.vspec, k * RS2);
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = gload(pl.jobs, jb);
@@ -425,12 +429,8 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
                 const float al = 0.5f * cw * a.get(), ap = 0.5f * cw * b.get();
                 float2 t = make_float2(__builtin_fmaf(al, z[k].x + mx, ap * (z[k].y + my)),
                                        __builtin_fmaf(al, z[k].y - my, -ap * (z[k].x - mx)));
-                if (jb > 0) {
-                    const float2 sv = bload2(rsh, it.vspec, k * RS2);
-                    t.x += sv.x;
-                    t.y += sv.y;
-                }
-                bstore2(t, rsh, it.vspec, k * RS2);
+                const float2 sv = bload2(rsh, it.vspec, k * RS2);
+                bstore2(make_float2(t.x + sv.x, t.y + sv.y), rsh, it.vspec, k * RS2);
                 a.next();
                 b.next();
                 QDVM_CHUNK_FENCE(k);

@@ -594,6 +594,12 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
             for (int k = 0; k < N; ++k) bstore(0.f, cl.q, (tid + q * T) * 4, k * RS);
     }
+    // the accumulator starts at zero (an unconditional read-modify-write in the
+    // job loop keeps that loop free of per-element branches)
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k <= N / 2; ++k) bstore2(make_float2(0.f, 0.f), rsh, (tid + q * T) * 8, k * RS2);
     // the jobs read mirrored pencils of the spectrum and of R, written by other threads
     __syncthreads();
 
@@ -654,12 +660,8 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
                 const float2 u = z[q][k], m = um[q][k];
                 float2 t = make_float2(__builtin_fmaf(al, u.x + m.x, a2 * (u.y + m.y)),
                                        __builtin_fmaf(al, u.y - m.y, -a2 * (u.x - m.x)));
-                if (jb > jb0) {
-                    const float2 sv = bload2(rsh, pi * 8, k * RS2);
-                    t.x += sv.x;
-                    t.y += sv.y;
-                }
-                bstore2(t, rsh, pi * 8, k * RS2);
+                const float2 sv = bload2(rsh, pi * 8, k * RS2);
+                bstore2(make_float2(t.x + sv.x, t.y + sv.y), rsh, pi * 8, k * RS2);
                 a.next();
                 QDVM_FENCE3(k);
             }
