@@ -308,11 +308,27 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
         }
         job2d_multiply<N>(z, fh, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);                  // line(f) + i plane(f)
+        if constexpr (STAGE) {
+            // the parked transform of g, read a chunk at a time before use
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const float2 t = STAGE ? bload2(rtg, it.vspec, i * RS2) : tg[i];
-            const float gain = __builtin_fmaf(t.x, z[i].y, (z[i].x - t.x) * t.y);
-            acc[i] = __builtin_fmaf(cw, gain, acc[i]);
+            for (int i0 = 0; i0 < N; i0 += 8) {
+                float2 t[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) t[i] = bload2(rtg, it.vspec, (i0 + i) * RS2);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const float gain = __builtin_fmaf(t[i].x, z[i0 + i].y, (z[i0 + i].x - t[i].x) * t[i].y);
+                    acc[i0 + i] = __builtin_fmaf(cw, gain, acc[i0 + i]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const float gain = __builtin_fmaf(tg[i].x, z[i].y, (z[i].x - tg[i].x) * tg[i].y);
+                acc[i] = __builtin_fmaf(cw, gain, acc[i]);
+            }
         }
     }
 
