@@ -167,3 +167,36 @@ def test_argument_errors(gpu_lib):
         with pytest.raises(gpu_lib.QdvmError) as ei:
             gpu_lib.AdaptivePlan(*args)
         assert ei.value.status == status, args
+
+
+def test_graph_capture_replays(gpu_lib):
+    """The three launches of an adaptive evaluation allocate nothing and clear
+    the level counters with a kernel, so the evaluation can be captured into a
+    graph; every replay (with eager work in between) equals the eager result."""
+    import torch
+    n, cells = 32, 40
+    f, _ = workloads.relaxation_mix(51, cells, 2, n)
+    plans = _levels_plans(gpu_lib, 2, n, (4, 8, 16), "near_equilibrium")
+    offs = np.arange(cells, dtype=np.int64) * n * n
+    ad = gpu_lib.AdaptivePlan(plans, offs, THR)
+    x = _dev(f.reshape(-1))
+    ref = ad.eval(x)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    q = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ad.eval(x, out=q, stream=s)          # warm-up on the capture stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ad.eval(x, out=q, stream=s)
+    torch.cuda.synchronize()
+    for r in range(3):
+        q.fill_(-1.0)
+        other = ad.eval(x)                   # eager work between the replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(q.cpu().numpy(), ref), r
+        assert np.array_equal(other.cpu().numpy(), ref), r
