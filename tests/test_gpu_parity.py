@@ -292,3 +292,34 @@ def test_fft_variants_and_autotune(gpu_lib, d, n, P, batch):
     assert per_cell_rel_linf(_eval(plan, f), ref, n ** d).max() <= TOL
     with pytest.raises(gpu_lib.QdvmError):
         plan.set_variant(0, 7)
+
+
+# the largest truncation 2 Nt + 1 <= n (its Dirichlet table fills the LDS left
+# beside the transpose buffers; at 3D n = 32 the evaluation then uses exactly
+# 160 KiB of LDS) and the smallest, Nt = 1
+@pytest.mark.parametrize("d,n,nt,P,batch", [
+    (2, 16, 7, 8, 5), (2, 64, 31, 8, 3), (2, 32, 1, 8, 9), (3, 16, 7, 6, 2), (3, 24, 11, 4, 1),
+    (3, 32, 15, 3, 1), (3, 32, 1, 8, 2),
+])
+def test_extreme_truncation(gpu_lib, d, n, nt, P, batch):
+    f = workloads.random_positive(1300 + n + nt, d, n, batch)
+    plan = gpu_lib.Plan(d, n, 8.0, ntilde=nt, num_dirs=P)
+    assert plan.ntilde == nt
+    q = _eval(plan, f)
+    errs = per_cell_rel_linf(q, oracle_q(plan, f), n ** d)
+    print("d=%d n=%d Nt=%d P=%d max cell rel err %.3e" % (d, n, nt, P, errs.max()))
+    assert errs.max() <= TOL
+
+
+def test_extreme_truncation_adjoint(gpu_lib):
+    # the adjoint at the largest 3D truncation (same LDS budget as the evaluation)
+    from parity_util import oracle_vjp
+    import torch
+    f = workloads.random_positive(1400, 3, 32, 1)
+    c = np.random.default_rng(1401).standard_normal(f.shape).astype(np.float32)
+    plan = gpu_lib.Plan(3, 32, 8.0, ntilde=15, num_dirs=2)
+    gf, gw = plan.vjp(_dev(f), _dev(c))
+    torch.cuda.synchronize()
+    rf, rw = oracle_vjp(plan, f, c)
+    assert rel_linf(gf.cpu().numpy(), rf) <= TOL
+    assert rel_linf(gw.cpu().numpy(), rw) <= TOL
