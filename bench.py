@@ -227,7 +227,7 @@ def main():
                     help="run only this secondary workload's timed loop (for counter collection) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(cells shard across GPUs without communication; see the design notes).", file=sys.stderr)
         sys.exit(2)
 

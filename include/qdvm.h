@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
     QDVM_OK = 0,
     QDVM_EINVAL = -1,        /* invalid argument (null pointer, bad size, bad direction...) */
-    QDVM_EUNSUPPORTED = -2,  /* valid request this build does not implement (grid size) */
+    QDVM_EUNSUPPORTED = -2,  /* a valid request outside the compiled set (grid size) */
     QDVM_ENOMEM = -3,        /* device allocation failed */
     QDVM_EDEVICE = -4        /* HIP runtime or kernel failure */
 } qdvm_status;
