@@ -31,3 +31,26 @@ def per_cell_rel_linf(got, ref, npts):
     got = np.asarray(got, np.float64).reshape(-1, npts)
     ref = np.asarray(ref, np.float64).reshape(-1, npts)
     return np.max(np.abs(got - ref), axis=1) / np.max(np.abs(ref), axis=1)
+
+
+def loss_total(plan, f):
+    """sum_i f_i l_i, l = sum_p w_p (line * plane convolution of f), via numpy FFTs."""
+    n, d = plan.n, plan.dim
+    f = np.asarray(f, np.float64).reshape((n,) * d)
+    F = np.fft.fftn(f)
+    tot = np.zeros_like(f)
+    import itertools
+    box = list(itertools.product(range(-plan.ntilde, plan.ntilde + 1), repeat=d))
+    for e, w, M in zip(plan.dirs, np.float32(plan.weights).astype(np.float64), plan.line_len):
+        if M == 0:
+            continue
+        IK = np.zeros(f.shape)
+        for m in range(-M, M + 1):
+            if m:
+                IK[tuple((m * e) % n)] += 1.0
+        IL = np.zeros(f.shape)
+        for l in box:
+            if int(np.dot(l, e)) == 0:
+                IL[tuple(np.array(l) % n)] += 1.0
+        tot += w * np.fft.ifftn(F * np.fft.fftn(IK) * np.fft.fftn(IL)).real
+    return float(np.sum(f * tot))

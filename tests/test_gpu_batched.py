@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_1201_3986_amd import workloads
-from parity_util import oracle_q, rel_linf
+from parity_util import loss_total, oracle_q, rel_linf
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -20,29 +20,6 @@ TOL = 1e-5
 def _dev(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
-
-
-def loss_total(plan, f):
-    """sum_i f_i l_i, l = sum_p w_p (line * plane convolution of f), via numpy FFTs."""
-    n, d = plan.n, plan.dim
-    f = np.asarray(f, np.float64).reshape((n,) * d)
-    F = np.fft.fftn(f)
-    tot = np.zeros_like(f)
-    import itertools
-    box = list(itertools.product(range(-plan.ntilde, plan.ntilde + 1), repeat=d))
-    for e, w, M in zip(plan.dirs, np.float32(plan.weights).astype(np.float64), plan.line_len):
-        if M == 0:
-            continue
-        IK = np.zeros(f.shape)
-        for m in range(-M, M + 1):
-            if m:
-                IK[tuple((m * e) % n)] += 1.0
-        IL = np.zeros(f.shape)
-        for l in box:
-            if int(np.dot(l, e)) == 0:
-                IL[tuple(np.array(l) % n)] += 1.0
-        tot += w * np.fft.ifftn(F * np.fft.fftn(IK) * np.fft.fftn(IL)).real
-    return float(np.sum(f * tot))
 
 
 def assert_same_cell(plan, got, single):

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1201_3986_amd import workloads
-from parity_util import oracle_q, per_cell_rel_linf, rel_linf
+from parity_util import loss_total, oracle_q, per_cell_rel_linf, rel_linf
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -252,6 +252,27 @@ def test_headline_size_sampled(gpu_lib):
     # every cell is the tiled copy of its base cell: identical inputs, identical outputs
     assert np.array_equal(q[:64], q[B - 64:])
     assert np.all(np.isfinite(q))
+
+
+@pytest.mark.parametrize("P", [8, 16])
+def test_3d_benchmark_size_sampled(gpu_lib, P):
+    # the benchmark's 3D launch: 2048 cells of 3D n=32 (64 distinct cells tiled)
+    # in one call; sampled cells against the oracle, every cell's mass balance
+    B = 2048
+    base = workloads.three_gaussians_batch(303, 64, 32)
+    f = np.ascontiguousarray(np.tile(base, (B // 64, 1, 1, 1)))
+    plan = gpu_lib.Plan(3, 32, 8.0, num_dirs=P)
+    q = _eval(plan, f).reshape(B, -1)
+    for c in (5, B - 1):
+        err = rel_linf(q[c], oracle_q(plan, f[c]))
+        print("P=%d cell %d rel err %.2e" % (P, c, err))
+        assert err <= TOL
+    assert np.array_equal(q[:64], q[B - 64:])
+    # mass: sum Q = 0 per cell, relative to the total loss sum_i f_i l_i
+    qs = q.astype(np.float64)
+    for c in range(0, 64, 9):
+        res = abs(qs[c].sum()) / loss_total(plan, f[c])
+        assert res <= 1e-6, (c, res)
 
 
 def test_3d_order2_direction_set(gpu_lib):
