@@ -65,34 +65,6 @@ __device__ __forceinline__ void inv2d(float2 (&z)[N], float* xb, int j)
     fftp<N, RV, 1>(z);
 }
 
-// Indices into the Dirichlet table for a job at (K0 = j, K1 = k): s = e.K,
-// t = e_perp.K (mod n), with e_perp = (-e1, e0); both advance linearly in K1.
-struct Mult2D {
-    int s, t, ds, dt;
-    const float* D;
-};
-
-template <int N>
-__device__ __forceinline__ Mult2D mult2d_init(const JobDesc& J, const float* dtab, int j)
-{
-    Mult2D m;
-    m.s = modc<N>(J.e[0] * j);
-    m.t = modc<N>(-J.e[1] * j);
-    m.ds = modc<N>(J.e[1]);
-    m.dt = modc<N>(J.e[0]);
-    m.D = dtab + J.M * N;
-    return m;
-}
-
-template <int N>
-__device__ __forceinline__ void mult2d_step(Mult2D& m)
-{
-    m.s += m.ds;
-    m.s -= (m.s >= N) ? N : 0;
-    m.t += m.dt;
-    m.t -= (m.t >= N) ? N : 0;
-}
-
 // Buffers of one workgroup item (cpb consecutive cells).
 struct Item2D {
     rsrc_t f, q, fh;     // cell data and the block's spectral scratch
