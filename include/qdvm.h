@@ -229,6 +229,9 @@ qdvm_status qdvm_step_graph_destroy(qdvm_graph_t graph);   /* synchronises the d
  *                outlive the adaptive batch).  List them by increasing cost
  *                (fewest directions first): the launch drains the last first.
  *   threshold:   host, nlevels - 1 finite, strictly increasing values.
+ * The adaptive batch holds its level queues, counters and spectral slots on
+ * the device: calls on one adaptive batch must be ordered (one stream, or
+ * externally serialised).
  * Errors: EINVAL (null or inconsistent arguments), EUNSUPPORTED (a grid outside
  * the batched set), ENOMEM / EDEVICE.
  */
