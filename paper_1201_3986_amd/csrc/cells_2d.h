@@ -86,20 +86,43 @@ __device__ __forceinline__ HalfSpec<N, N * 8> half2d(rsrc_t r, int vspec, int j)
 // weight is applied to the product, not folded into alpha: the real and
 // imaginary parts of one complex transform must be of the same size, or the
 // rounding of the larger one swamps the smaller.)
-template <int N>
+// C > 0: the spectrum is read in chunks of C elements, each chunk's reads issued
+// before any of them is used (for code whose register budget would otherwise
+// lead the scheduler to wait for each read in turn); C = 0: reads interleaved
+// with their use, fenced every 8 elements.
+template <int N, int C = 0>
 __device__ __forceinline__ void job2d_multiply(float2 (&z)[N], const HalfSpec<N, N * 8>& hs, const JobDesc& J,
                                                const float* dtab, const float* atab, int j)
 {
     RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * j), modc<N>(J.e[1]));
     RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
+    if constexpr (C == 0) {
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float2 F = hs.get(k);
-        const float al = a.get(), ap = b.get();
-        z[k] = make_float2(__builtin_fmaf(al, F.x, -ap * F.y), __builtin_fmaf(al, F.y, ap * F.x));
-        a.next();
-        b.next();
-        QDVM_CHUNK_FENCE(k);
+        for (int k = 0; k < N; ++k) {
+            const float2 F = hs.get(k);
+            const float al = a.get(), ap = b.get();
+            z[k] = make_float2(__builtin_fmaf(al, F.x, -ap * F.y), __builtin_fmaf(al, F.y, ap * F.x));
+            a.next();
+            b.next();
+            QDVM_CHUNK_FENCE(k);
+        }
+    } else {
+#pragma unroll
+        for (int k0 = 0; k0 < N; k0 += C) {
+            float2 F[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i) F[i] = hs.get(k0 + i);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const float al = a.get(), ap = b.get();
+                z[k0 + i] = make_float2(__builtin_fmaf(al, F[i].x, -ap * F[i].y),
+                                        __builtin_fmaf(al, F[i].y, ap * F[i].x));
+                a.next();
+                b.next();
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 }
 
@@ -305,6 +328,197 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
     }
 
     if (!valid) return;
+    if (dt == 0.f) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
+    } else {
+        float fv[N];
+        load_run<N>(fv, it.f, reread(it.vcell), 0, RS);
+#pragma unroll
+        for (int i = 0; i < N; ++i) bstore(__builtin_fmaf(dt, acc[i], fv[i]), it.q, it.vcell, i * RS);
+    }
+}
+
+// The near-equilibrium evaluation with two waves per cell, for n = 64, where
+// one pencil fills half of a lane's registers: a wave that held both transforms
+// of a job and the accumulator ran at one wave per SIMD.  Here the g wave forms
+// every transform of g = f - M and the f wave every transform of f, each in its
+// own LDS slot (xg, xf).  A job's gain is split between the two accumulators,
+//     line(g) (plane(f) - plane(g))    in the g wave,
+//     line(f) plane(g)                 in the f wave,
+// (together line(g) plane(f) + line(M) plane(g), each term of size |f| |g|),
+// so that each wave hands the other only its plane field, through its own
+// slot.  The f wave's accumulator joins the g wave's at the end, which writes
+// the result.  All waves of the workgroup run the same number of cells.
+// A double that is the same in every lane of the wave, moved to scalar registers.
+__device__ __forceinline__ double uniform(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int N, int RV>
+__device__ __forceinline__ void cell2d_eval_split_pair(const DevPlan& pl, const Item2D& it, rsrc_t rgh,
+                                                       rsrc_t rlam, const float* __restrict__ jobw, float dt,
+                                                       bool valid, float* xg, float* xf, const float* dtab, int j,
+                                                       bool fwave)
+{
+    static_assert(N == 64, "one cell per wave: lane j holds column j");
+    constexpr int RS = N * 4;
+    float* own = fwave ? xf : xg;
+    const float* other = fwave ? xg : xf;
+    // the previous cell's last hand-over has been read from both slots
+    __syncthreads();
+    double ej = 0.0, mu0 = 0.0, inv2v = 0.0;
+    float2 z[N];
+    if (fwave) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
+    } else {
+        // moments in index units (column j holds the points (i, j)), FP64
+        double s0 = 0.0, sa = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += 16) {
+            float fv[16];
+            load_run<16>(fv, it.f, it.vcell, i0, RS);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const double v = fv[i];
+                s0 += v;
+                sa += (double)(i0 + i) * v;
+                s2 += (double)((i0 + i) * (i0 + i)) * v;
+            }
+        }
+        double sb = (double)j * s0;
+        s2 += (double)(j * j) * s0;
+        s0 = group_sumd<N>(s0);
+        sa = group_sumd<N>(sa);
+        sb = group_sumd<N>(sb);
+        s2 = group_sumd<N>(s2);
+        const double m0 = sa / s0, m1 = sb / s0;
+        const double var = 0.5 * (s2 / s0 - m0 * m0 - m1 * m1);
+        const bool ok = s0 > 0.0 && var > 0.25 && __builtin_isfinite(var) && __builtin_isfinite(m0) &&
+                        __builtin_isfinite(m1);
+        // the moments are sums over the whole wave: uniform, kept in scalar registers
+        mu0 = uniform(ok ? m0 : 0.0);
+        const double mu1 = ok ? m1 : 0.0;
+        inv2v = uniform(ok ? 0.5 / var : 0.0);
+        ej = ok ? s0 / (2.0 * kPi * var) * exp(-(j - mu1) * (j - mu1) * inv2v) : 0.0;
+        // M(i, j) = ej e_i: the n factors e_i are the same in every lane; lane
+        // j forms e_j, in the wave's own slot (free until its transform)
+        double* ex = reinterpret_cast<double*>(xg);
+        ex[j] = exp(-(j - mu0) * (j - mu0) * inv2v);
+        wave_sync();
+        const int vc = reread(it.vcell);
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += 16) {
+            float fv[16];
+            double e[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) e[i] = ex[i0 + i];
+            load_run<16>(fv, it.f, vc, i0, RS);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) z[i0 + i] = make_float2((float)((double)fv[i] - ej * e[i]), 0.f);
+        }
+    }
+    fwd2d<N, RV>(z, own, j);
+    const HalfSpec<N, N * 8> sp = half2d<N>(fwave ? it.fh : rgh, it.vspec, j);
+    sp.put(z);
+#pragma unroll
+    for (int k0 = 0; k0 < N; k0 += 16) {
+        float l[16];
+        load_run<16>(l, rlam, j * 4, k0, RS);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            z[k0 + k].x *= l[k];
+            z[k0 + k].y *= l[k];
+        }
+    }
+    inv2d<N, RV>(z, own, j);                     // l(g) or l(f)
+    // loss g l(f) + M l(g): the f wave hands l(f) over (its slot is free once
+    // every lane of the wave has read its transpose)
+    if (fwave) {
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < N; ++i) xf[i * N + j] = z[i].x;
+    }
+    __syncthreads();
+    float acc[N];
+    if (fwave) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] = 0.f;
+    } else {
+        // the factors e_i again, in the own slot (free after the transform)
+        double* ex = reinterpret_cast<double*>(xg);
+        wave_sync();
+        ex[j] = exp(-(j - mu0) * (j - mu0) * inv2v);
+        wave_sync();
+        const int vc = reread(it.vcell);
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += 16) {
+            float fv[16], lf[16];
+            double e[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                e[i] = ex[i0 + i];
+                lf[i] = xf[(i0 + i) * N + j];
+            }
+            load_run<16>(fv, it.f, vc, i0, RS);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const double m = ej * e[i];
+                const float g = (float)((double)fv[i] - m);
+                acc[i0 + i] = -__builtin_fmaf(g, lf[i], (float)m * z[i0 + i].x);
+            }
+        }
+    }
+
+    // per job: line + i plane of this wave's function, then the other wave's plane
+    const float sub = fwave ? 0.f : 1.f;
+    const float* atab = dtab_alpha(dtab, pl);
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(jobw, jb);
+        job2d_multiply<N, 8>(z, sp, J, dtab, atab, j);
+        __syncthreads();                         // the other wave has read this slot
+        inv2d<N, RV>(z, own, j);
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < N; ++i) own[i * N + j] = z[i].y;
+        __syncthreads();
+        // the other wave's plane, read a chunk at a time before use
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += 16) {
+            float o[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) o[i] = other[(i0 + i) * N + j];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float t = __builtin_fmaf(-sub, z[i0 + i].y, o[i]);
+                acc[i0 + i] = __builtin_fmaf(cw * z[i0 + i].x, t, acc[i0 + i]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    __syncthreads();                             // both planes of the last job have been read
+    if (fwave) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) xf[i * N + j] = acc[i];
+    }
+    __syncthreads();
+    if (fwave || !valid) return;
+#pragma unroll
+    for (int i0 = 0; i0 < N; i0 += 16) {
+        float a2[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a2[i] = xf[(i0 + i) * N + j];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i0 + i] += a2[i];
+    }
     if (dt == 0.f) {
 #pragma unroll
         for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);

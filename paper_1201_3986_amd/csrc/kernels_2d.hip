@@ -66,6 +66,37 @@ __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const flo
     }
 }
 
+// Near-equilibrium mode at n = 64: one cell per workgroup of two waves
+// (cell2d_eval_split_pair), persistent over cells.  The workgroup's barriers
+// then pair only the two waves of one cell, and its LDS (two transpose slots
+// and the Dirichlet tables, 40 KiB at the default truncation) lets four such
+// workgroups share a CU.
+template <int RV>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_eval2d_pair(
+    DevPlan pl, int batch, const float* f, float* q, float dt, DevScratch s)
+{
+    constexpr int N = 64, SLOT = N * (N + 1), NPTS = N * N;
+    extern __shared__ float smem[];
+    const int tid = threadIdx.x, j = tid & 63;
+    const bool fwave = __builtin_amdgcn_readfirstlane(tid >> 6) != 0;
+    float* xg = smem;
+    float* xf = smem + SLOT;
+    float* dtab = smem + 2 * SLOT;
+    load_dtab(dtab, pl, tid, blockDim.x);
+    __syncthreads();
+    const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
+    Item2D it;
+    it.fh = make_rsrc(s.spec + (size_t)blockIdx.x * NPTS, NPTS * 8);
+    it.vcell = j * 4;
+    it.vspec = j * 8;
+    const rsrc_t rgh = make_rsrc(s.spec2 + (size_t)blockIdx.x * NPTS, NPTS * 8);
+    for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
+        it.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
+        it.q = make_rsrc(q + (size_t)cell * NPTS, NPTS * 4);
+        cell2d_eval_split_pair<N, RV>(pl, it, rgh, rlam, s.jobw, dt, true, xg, xf, dtab, j, fwave);
+    }
+}
+
 template <int N, int RV>
 __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const float* __restrict__ f,
                                                const float* __restrict__ c, float* __restrict__ g,
@@ -125,6 +156,14 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
         li.block = 256;
         li.lds = lds2d<N>(pl.ntilde);
         const int items = (batch + 256 / N - 1) / (256 / N);
+        if (pl.mode && N == 64) {
+            li.block = 128;
+            li.lds = sizeof(float) * ((size_t)2 * N * (N + 1) + (size_t)2 * (pl.ntilde + 1) * N);
+            e = variant ? occupancy_grid(k_eval2d_pair<1>, 128, li.lds, batch, li.grid)
+                        : occupancy_grid(k_eval2d_pair<0>, 128, li.lds, batch, li.grid);
+            li.slots = li.grid;
+            return e;
+        }
         if (pl.mode)
             e = variant ? occupancy_grid(k_eval2d<N, 1, true>, 256, li.lds, items, li.grid)
                         : occupancy_grid(k_eval2d<N, 0, true>, 256, li.lds, items, li.grid);
@@ -141,7 +180,10 @@ hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q,
 {
     QDVM_SWITCH_2D(pl.n, {
         const dim3 g(li.grid), b(256);
-        if (pl.mode) {
+        if (pl.mode && N == 64) {
+            if (variant) hipLaunchKernelGGL((k_eval2d_pair<1>), g, dim3(128), li.lds, st, pl, batch, f, q, dt, s);
+            else hipLaunchKernelGGL((k_eval2d_pair<0>), g, dim3(128), li.lds, st, pl, batch, f, q, dt, s);
+        } else if (pl.mode) {
             if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
             else hipLaunchKernelGGL((k_eval2d<N, 0, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
         } else {
