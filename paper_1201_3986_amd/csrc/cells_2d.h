@@ -165,7 +165,7 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
-        job2d_multiply<N>(z, fh, J, dtab, atab, j);
+        job2d_multiply<N, (N == 64 ? 0 : (N < 8 ? N : 8))>(z, fh, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);
 #pragma unroll
         for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
@@ -215,13 +215,19 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
 {
     constexpr int RS = N * 4, RS2 = N * 8;
     // moments in index units (column j holds the points (i, j)), FP64
+    constexpr int C = N < 16 ? N : 16;   // elements per read chunk
     double s0 = 0.0, sa = 0.0, s2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const double v = bload(it.f, it.vcell, i * RS);
-        s0 += v;
-        sa += (double)i * v;
-        s2 += (double)(i * i) * v;
+    for (int i0 = 0; i0 < N; i0 += C) {
+        float fv[C];
+        load_run<C>(fv, it.f, it.vcell, i0, RS);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const double v = fv[i];
+            s0 += v;
+            sa += (double)(i0 + i) * v;
+            s2 += (double)((i0 + i) * (i0 + i)) * v;
+        }
     }
     double sb = (double)j * s0;
     s2 += (double)(j * j) * s0;
@@ -243,19 +249,24 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
 
     float2 z[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        z[i] = make_float2((float)((double)bload(it.f, it.vcell, i * RS) - QDVM_MAXW(i)), 0.f);
-        QDVM_CHUNK_FENCE(i);
+    for (int i0 = 0; i0 < N; i0 += C) {
+        float fv[C];
+        load_run<C>(fv, it.f, it.vcell, i0, RS);
+#pragma unroll
+        for (int i = 0; i < C; ++i) z[i0 + i] = make_float2((float)((double)fv[i] - QDVM_MAXW(i0 + i)), 0.f);
     }
     fwd2d<N, RV>(z, xb, j);
     const HalfSpec<N, N * 8> gh = half2d<N>(rgh, it.vspec, j), fh = half2d<N>(it.fh, it.vspec, j);
     gh.put(z);
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float l = bload(rlam, j * 4, k * RS);
-        z[k].x *= l;
-        z[k].y *= l;
-        QDVM_CHUNK_FENCE(k);
+    for (int k0 = 0; k0 < N; k0 += C) {
+        float l[C];
+        load_run<C>(l, rlam, j * 4, k0, RS);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            z[k0 + k].x *= l[k];
+            z[k0 + k].y *= l[k];
+        }
     }
     inv2d<N, RV>(z, xb, j);                      // l(g)
     float acc[N];                                // holds l(g) until l(f) is formed
@@ -269,11 +280,14 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
     fwd2d<N, RV>(z, xb, j);
     fh.put(z);
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float l = bload(rlam, j * 4, k * RS);
-        z[k].x *= l;
-        z[k].y *= l;
-        QDVM_CHUNK_FENCE(k);
+    for (int k0 = 0; k0 < N; k0 += C) {
+        float l[C];
+        load_run<C>(l, rlam, j * 4, k0, RS);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            z[k0 + k].x *= l[k];
+            z[k0 + k].y *= l[k];
+        }
     }
     inv2d<N, RV>(z, xb, j);                      // l(f)
     {
@@ -281,11 +295,15 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
         const double iv = opaque(inv2v), m0 = opaque(mu0);
         const int vc = reread(it.vcell);
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const double m = ej * exp(-((i) - m0) * ((i) - m0) * iv);
-            const float g = (float)((double)bload(it.f, vc, i * RS) - m);
-            acc[i] = -__builtin_fmaf(g, z[i].x, (float)m * acc[i]);
-            QDVM_CHUNK_FENCE(i);
+        for (int i0 = 0; i0 < N; i0 += C) {
+            float fv[C];
+            load_run<C>(fv, it.f, vc, i0, RS);
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const double m = ej * exp(-((i0 + i) - m0) * ((i0 + i) - m0) * iv);
+                const float g = (float)((double)fv[i] - m);
+                acc[i0 + i] = -__builtin_fmaf(g, z[i0 + i].x, (float)m * acc[i0 + i]);
+            }
         }
     }
 #undef QDVM_MAXW
@@ -295,13 +313,13 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
         float2 tg[N];
-        job2d_multiply<N>(tg, gh, J, dtab, atab, j);
+        job2d_multiply<N, (N < 8 ? N : 8)>(tg, gh, J, dtab, atab, j);
         inv2d<N, RV>(tg, xb, j);                 // line(g) + i plane(g)
         if constexpr (STAGE) {
 #pragma unroll
             for (int i = 0; i < N; ++i) bstore2(tg[i], rtg, it.vspec, i * RS2);
         }
-        job2d_multiply<N>(z, fh, J, dtab, atab, j);
+        job2d_multiply<N, (N < 8 ? N : 8)>(z, fh, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);                  // line(f) + i plane(f)
         if constexpr (STAGE) {
             // the parked transform of g, read a chunk at a time before use
@@ -554,11 +572,21 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
     for (int i = 0; i < N; ++i)
         z[i] = make_float2(bload(rc, it.vcell, i * RS) * bload(it.f, it.vcell, i * RS), 0.f);
     fwd2d<N, RV>(z, xb, j);
-    // R = Re(conj F(cf) fhat) on the own half row (written by this lane)
+    // R = Re(conj F(cf) fhat) on the own half row (written by this lane); the
+    // reads of a chunk are issued before its stores, which the compiler cannot
+    // tell apart from them
 #pragma unroll
-    for (int k = 0; k <= N / 2; ++k) {
-        const float2 F = fh.get(k);
-        bstore(__builtin_fmaf(z[k].x, F.x, z[k].y * F.y), rr, rown, k * RS);
+    for (int k0 = 0; k0 <= N / 2; k0 += 8) {
+        constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;
+        float2 F[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            if (k0 + i <= N / 2) F[i] = fh.get(k0 + i);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            if (k0 + i <= N / 2)
+                bstore(__builtin_fmaf(z[k0 + i].x, F[i].x, z[k0 + i].y * F[i].y), rr, rown, (k0 + i) * RS);
     }
     // IFFT(Lambda (fhat + i F(cf))) = l + i C_Lambda(cf)
 #pragma unroll
@@ -624,18 +652,30 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * jj), modc<N>(J.e[1]));
             RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * jj), modc<N>(J.e[0]));
 #pragma unroll
-            for (int k = 0; k <= N / 2; ++k) {
-                // Hermitian part of (alpha - i alpha') uhat: uhat(-K) is element
-                // n - k of the mirror row
-                const float mx = __shfl(z[(N - k) % N].x, mlane, 64), my = __shfl(z[(N - k) % N].y, mlane, 64);
-                const float al = 0.5f * cw * a.get(), ap = 0.5f * cw * b.get();
-                float2 t = make_float2(__builtin_fmaf(al, z[k].x + mx, ap * (z[k].y + my)),
-                                       __builtin_fmaf(al, z[k].y - my, -ap * (z[k].x - mx)));
-                const float2 sv = bload2(rsh, it.vspec, k * RS2);
-                bstore2(make_float2(t.x + sv.x, t.y + sv.y), rsh, it.vspec, k * RS2);
-                a.next();
-                b.next();
-                QDVM_CHUNK_FENCE(k);
+            for (int k0 = 0; k0 <= N / 2; k0 += 8) {
+                // the chunk's accumulator reads go out before its stores (the
+                // compiler would otherwise wait for each read in turn)
+                constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;
+                float2 sv[C];
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    if (k0 + i <= N / 2) sv[i] = bload2(rsh, it.vspec, (k0 + i) * RS2);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const int k = k0 + i;
+                    if (k > N / 2) break;
+                    // Hermitian part of (alpha - i alpha') uhat: uhat(-K) is element
+                    // n - k of the mirror row
+                    const float mx = __shfl(z[(N - k) % N].x, mlane, 64), my = __shfl(z[(N - k) % N].y, mlane, 64);
+                    const float al = 0.5f * cw * a.get(), ap = 0.5f * cw * b.get();
+                    float2 t = make_float2(__builtin_fmaf(al, z[k].x + mx, ap * (z[k].y + my)),
+                                           __builtin_fmaf(al, z[k].y - my, -ap * (z[k].x - mx)));
+                    bstore2(make_float2(t.x + sv[i].x, t.y + sv[i].y), rsh, it.vspec, k * RS2);
+                    a.next();
+                    b.next();
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }

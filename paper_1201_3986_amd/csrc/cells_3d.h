@@ -254,11 +254,14 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const float l = bload(rlam, (tid + q * T) * 4, k * RS);
-                z[q][k].x *= l;
-                z[q][k].y *= l;
-                QDVM_CHUNK_FENCE(k);
+            for (int k0 = 0; k0 < N; k0 += 8) {
+                float l[8];
+                load_run<8>(l, rlam, (tid + q * T) * 4, k0, RS);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    z[q][k0 + k].x *= l[k];
+                    z[q][k0 + k].y *= l[k];
+                }
             }
         inv3d<N, T, Q, RV>(z, xb, tid);
         constexpr int C = N % 8 == 0 ? 8 : N;
@@ -357,11 +360,16 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
         const int pi = tid + q * T, py = pi / N, pz = pi % N;
         double ps = 0.0;
 #pragma unroll
-        for (int x = 0; x < N; ++x) {
-            const double v = bload(cl.f, pi * 4, x * RS);
-            ps += v;
-            mom[1] += (double)x * v;
-            mom[4] += (double)(x * x) * v;
+        for (int x0 = 0; x0 < N; x0 += 8) {
+            float fv[8];
+            load_run<8>(fv, cl.f, pi * 4, x0, RS);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const double v = fv[i];
+                ps += v;
+                mom[1] += (double)(x0 + i) * v;
+                mom[4] += (double)((x0 + i) * (x0 + i)) * v;
+            }
         }
         mom[0] += ps;
         mom[2] += (double)py * ps;
@@ -387,25 +395,34 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
         eyz[q] = ok ? C * exp(-((py - my) * (py - my) + (pz - mz) * (pz - mz)) * inv2v) : 0.0;
     }
     __syncthreads();
-#define QDVM_MAXW3(q, x) (eyz[q] * ex[x])
 
     float2 z[Q][N];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int x = 0; x < N; ++x)
-            z[q][x] = make_float2((float)((double)bload(cl.f, (tid + q * T) * 4, x * RS) - QDVM_MAXW3(q, x)), 0.f);
+        for (int x0 = 0; x0 < N; x0 += 8) {
+            float fv[8];
+            double e[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) e[i] = ex[x0 + i];
+            load_run<8>(fv, cl.f, (tid + q * T) * 4, x0, RS);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) z[q][x0 + i] = make_float2((float)((double)fv[i] - eyz[q] * e[i]), 0.f);
+        }
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
     for (int q = 0; q < Q; ++q) half3d<N>(rgh, tid + q * T).put(z[q]);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const float l = bload(rlam, (tid + q * T) * 4, k * RS);
-            z[q][k].x *= l;
-            z[q][k].y *= l;
-            QDVM_CHUNK_FENCE(k);
+        for (int k0 = 0; k0 < N; k0 += 8) {
+            float l[8];
+            load_run<8>(l, rlam, (tid + q * T) * 4, k0, RS);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                z[q][k0 + k].x *= l[k];
+                z[q][k0 + k].y *= l[k];
+            }
         }
     inv3d<N, T, Q, RV>(z, xb, tid);             // l(g)
     float acc[Q][N];                            // holds l(g) until l(f) is formed
@@ -423,11 +440,14 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const float l = bload(rlam, (tid + q * T) * 4, k * RS);
-            z[q][k].x *= l;
-            z[q][k].y *= l;
-            QDVM_CHUNK_FENCE(k);
+        for (int k0 = 0; k0 < N; k0 += 8) {
+            float l[8];
+            load_run<8>(l, rlam, (tid + q * T) * 4, k0, RS);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                z[q][k0 + k].x *= l[k];
+                z[q][k0 + k].y *= l[k];
+            }
         }
     inv3d<N, T, Q, RV>(z, xb, tid);             // l(f)
     {
@@ -435,13 +455,21 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int x = 0; x < N; ++x) {
-                const double m = QDVM_MAXW3(q, x);
-                const float g = (float)((double)bload(cl.f, (tid + q * T) * 4, x * RS) - m);
-                acc[q][x] = -__builtin_fmaf(g, z[q][x].x, (float)m * acc[q][x]);
+            for (int x0 = 0; x0 < N; x0 += 8) {
+                float fv[8];
+                double e[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) e[i] = ex[x0 + i];
+                load_run<8>(fv, cl.f, (tid + q * T) * 4, x0, RS);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int x = x0 + i;
+                    const double m = eyz[q] * e[i];
+                    const float g = (float)((double)fv[i] - m);
+                    acc[q][x] = -__builtin_fmaf(g, z[q][x].x, (float)m * acc[q][x]);
+                }
             }
     }
-#undef QDVM_MAXW3
 
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
@@ -461,10 +489,17 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int x = 0; x < N; ++x) {
-                const float2 t = STAGE ? bload2(rtg, (tid + q * T) * 8, x * RS2) : tg[q][x];
-                const float gain = __builtin_fmaf(t.x, z[q][x].y, (z[q][x].x - t.x) * t.y);
-                acc[q][x] = __builtin_fmaf(cw, gain, acc[q][x]);
+            for (int x0 = 0; x0 < N; x0 += 8) {
+                float2 t[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) t[i] = STAGE ? bload2(rtg, (tid + q * T) * 8, (x0 + i) * RS2) : tg[q][x0 + i];
+                if constexpr (STAGE) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int x = x0 + i;
+                    const float gain = __builtin_fmaf(t[i].x, z[q][x].y, (z[q][x].x - t[i].x) * t[i].y);
+                    acc[q][x] = __builtin_fmaf(cw, gain, acc[q][x]);
+                }
             }
     }
 #pragma unroll
@@ -556,10 +591,20 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
     for (int q = 0; q < Q; ++q) {
         const int pi = tid + q * T;
         const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi);
+        // own half of the pencil, written by this lane; each chunk's reads are
+        // issued before its stores (which the compiler cannot tell apart from them)
 #pragma unroll
-        for (int k = 0; k <= N / 2; ++k) {   // own half of the pencil: written by this lane
-            const float2 F = fh.get(k);
-            bstore(__builtin_fmaf(z[q][k].x, F.x, z[q][k].y * F.y), rr, pi * 4, k * RS);
+        for (int k0 = 0; k0 <= N / 2; k0 += 4) {
+            float2 F[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (k0 + i <= N / 2) F[i] = fh.get(k0 + i);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (k0 + i <= N / 2)
+                    bstore(__builtin_fmaf(z[q][k0 + i].x, F[i].x, z[q][k0 + i].y * F[i].y), rr, pi * 4,
+                           (k0 + i) * RS);
         }
     }
     if (loss) {
@@ -654,16 +699,31 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
             const int pi = reread(tid + q * T), kx = pi / N, ky = pi % N;
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
-            for (int k = 0; k <= N / 2; ++k) {
-                const float al = 0.5f * cw * a.get(), a2 = 0.5f * cw * bload(rap, pi * 4, k * RS);
-                // (a/2)(u + conj m) - i (a'/2)(u - conj m), m = uhat(-K)
-                const float2 u = z[q][k], m = um[q][k];
-                float2 t = make_float2(__builtin_fmaf(al, u.x + m.x, a2 * (u.y + m.y)),
-                                       __builtin_fmaf(al, u.y - m.y, -a2 * (u.x - m.x)));
-                const float2 sv = bload2(rsh, pi * 8, k * RS2);
-                bstore2(make_float2(t.x + sv.x, t.y + sv.y), rsh, pi * 8, k * RS2);
-                a.next();
-                QDVM_FENCE3(k);
+            for (int k0 = 0; k0 <= N / 2; k0 += 4) {
+                // the chunk's reads go out before its stores (the compiler would
+                // otherwise wait for each accumulator read in turn)
+                float2 sv[4];
+                float a2[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (k0 + i <= N / 2) {
+                        sv[i] = bload2(rsh, pi * 8, (k0 + i) * RS2);
+                        a2[i] = 0.5f * cw * bload(rap, pi * 4, (k0 + i) * RS);
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = k0 + i;
+                    if (k > N / 2) break;
+                    const float al = 0.5f * cw * a.get();
+                    // (a/2)(u + conj m) - i (a'/2)(u - conj m), m = uhat(-K)
+                    const float2 u = z[q][k], m = um[q][k];
+                    float2 t = make_float2(__builtin_fmaf(al, u.x + m.x, a2[i] * (u.y + m.y)),
+                                           __builtin_fmaf(al, u.y - m.y, -a2[i] * (u.x - m.x)));
+                    bstore2(make_float2(t.x + sv[i].x, t.y + sv[i].y), rsh, pi * 8, k * RS2);
+                    a.next();
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }

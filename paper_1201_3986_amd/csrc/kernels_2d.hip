@@ -59,9 +59,9 @@ __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const flo
         const int nvalid = min(CPB, batch - first);
         it.f = make_rsrc(f + (size_t)first * NPTS, nvalid * NPTS * 4);
         it.q = make_rsrc(q + (size_t)first * NPTS, nvalid * NPTS * 4);
-        if constexpr (SPLIT)
+        if constexpr (SPLIT && N != 64)   // n = 64: k_eval2d_pair
             cell2d_eval_split<N, RV, STAGE>(pl, it, rgh, rtg, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
-        else
+        else if constexpr (!SPLIT)
             cell2d_eval<N, RV>(pl, it, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
     }
 }

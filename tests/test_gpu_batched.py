@@ -24,12 +24,14 @@ def _dev(a):
 
 def assert_same_cell(plan, got, single):
     """The batched launch runs the single-cell device code, so 2D cells match the
-    single-plan result bit for bit.  A small 3D batch through the single-plan
-    path spreads each cell's directions over several workgroups and adds their
-    parts in another order, so 3D cells agree to rounding."""
+    single-plan result bit for bit.  Two cases agree to rounding only: a small
+    3D batch through the single-plan path spreads each cell's directions over
+    several workgroups and adds their parts in another order, and a single
+    near-equilibrium 2D n = 64 plan runs the two-wave kernel, which splits each
+    job's gain over two accumulators."""
     got = np.asarray(got).reshape(-1)
     single = np.asarray(single).reshape(-1)
-    if plan.dim == 2:
+    if plan.dim == 2 and not (plan.n == 64 and plan.mode != 0):
         assert np.array_equal(got, single)
     else:
         assert rel_linf(got, single) <= 1e-6
