@@ -656,24 +656,33 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
                 // the chunk's accumulator reads go out before its stores (the
                 // compiler would otherwise wait for each read in turn)
                 constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;
-                float2 sv[C];
+                float2 sv[C], m[C], w[C];
 #pragma unroll
                 for (int i = 0; i < C; ++i)
-                    if (k0 + i <= N / 2) sv[i] = bload2(rsh, it.vspec, (k0 + i) * RS2);
+                    if (k0 + i <= N / 2) {
+                        sv[i] = bload2(rsh, it.vspec, (k0 + i) * RS2);
+                        w[i] = make_float2(a.get(), b.get());
+                        a.next();
+                        b.next();
+                    }
+                // Hermitian part of (alpha - i alpha') uhat: uhat(-K) is element
+                // n - k of the mirror row, another lane's
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    if (k0 + i <= N / 2) {
+                        const int k = k0 + i;
+                        m[i] = make_float2(__shfl(z[(N - k) % N].x, mlane, 64), __shfl(z[(N - k) % N].y, mlane, 64));
+                    }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int k = k0 + i;
                     if (k > N / 2) break;
-                    // Hermitian part of (alpha - i alpha') uhat: uhat(-K) is element
-                    // n - k of the mirror row
-                    const float mx = __shfl(z[(N - k) % N].x, mlane, 64), my = __shfl(z[(N - k) % N].y, mlane, 64);
-                    const float al = 0.5f * cw * a.get(), ap = 0.5f * cw * b.get();
+                    const float mx = m[i].x, my = m[i].y;
+                    const float al = 0.5f * cw * w[i].x, ap = 0.5f * cw * w[i].y;
                     float2 t = make_float2(__builtin_fmaf(al, z[k].x + mx, ap * (z[k].y + my)),
                                            __builtin_fmaf(al, z[k].y - my, -ap * (z[k].x - mx)));
                     bstore2(make_float2(t.x + sv[i].x, t.y + sv[i].y), rsh, it.vspec, k * RS2);
-                    a.next();
-                    b.next();
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }

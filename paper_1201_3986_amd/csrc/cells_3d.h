@@ -703,25 +703,26 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
                 // the chunk's reads go out before its stores (the compiler would
                 // otherwise wait for each accumulator read in turn)
                 float2 sv[4];
-                float a2[4];
+                float a2[4], a1[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     if (k0 + i <= N / 2) {
                         sv[i] = bload2(rsh, pi * 8, (k0 + i) * RS2);
                         a2[i] = 0.5f * cw * bload(rap, pi * 4, (k0 + i) * RS);
+                        a1[i] = 0.5f * cw * a.get();
+                        a.next();
                     }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int k = k0 + i;
                     if (k > N / 2) break;
-                    const float al = 0.5f * cw * a.get();
+                    const float al = a1[i];
                     // (a/2)(u + conj m) - i (a'/2)(u - conj m), m = uhat(-K)
                     const float2 u = z[q][k], m = um[q][k];
                     float2 t = make_float2(__builtin_fmaf(al, u.x + m.x, a2[i] * (u.y + m.y)),
                                            __builtin_fmaf(al, u.y - m.y, -a2[i] * (u.x - m.x)));
                     bstore2(make_float2(t.x + sv[i].x, t.y + sv[i].y), rsh, pi * 8, k * RS2);
-                    a.next();
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
