@@ -123,10 +123,13 @@ def test_degenerate_cells_fall_back_to_full(gpu_lib):
     assert rel_linf(q[3], ref[3]) <= TOL
 
 
-def test_euler_in_place_and_call_weights(gpu_lib):
+@pytest.mark.parametrize("n,cells", [(32, 10), (64, 7)])
+def test_euler_in_place_and_call_weights(gpu_lib, n, cells):
+    # n = 64 runs the two-wave kernel: the in-place update is written by one wave
+    # after both have read f
     import torch
-    f = _local_maxwellians(77, 2, 32, 10)
-    plan = gpu_lib.Plan(2, 32, 8.0, num_dirs=16, mode=NEAR)
+    f = _local_maxwellians(77, 2, n, cells)
+    plan = gpu_lib.Plan(2, n, 8.0, num_dirs=16, mode=NEAR)
     dt = 0.01
     ref = f.astype(np.float64) + dt * oracle_near(plan, f).reshape(f.shape)
     x = _dev(f)
@@ -137,7 +140,7 @@ def test_euler_in_place_and_call_weights(gpu_lib):
     w = rng.uniform(0.5, 2.0, size=plan.num_dirs).astype(np.float32)
     q = plan.eval(_dev(f), w=_dev(w))
     torch.cuda.synchronize()
-    errs = per_cell_rel_linf(q.cpu().numpy(), oracle_near(plan, f, w=w), 32 * 32)
+    errs = per_cell_rel_linf(q.cpu().numpy(), oracle_near(plan, f, w=w), n * n)
     assert errs.max() <= TOL
 
 
