@@ -154,3 +154,28 @@ def test_mass_conservation(gpu_lib):
         res = abs(q[c].sum()) / np.sum(np.abs(ref[c]))
         print("mass residual %.3e" % res)
         assert res <= 1e-6
+
+
+def test_two_wave_kernel_edge_cases(gpu_lib):
+    """2D n = 64 (one cell per two-wave workgroup): an empty batch, one cell, a
+    truncation other than the default (smaller Dirichlet tables, so another LDS
+    size and workgroups per CU), an explicit direction set holding a line longer
+    than the truncation (M = 0), and a NaN cell beside a finite one."""
+    import torch
+    plan = gpu_lib.Plan(2, 64, 8.0, num_dirs=8, mode=NEAR)
+    assert plan.eval(torch.empty(0, dtype=torch.float32, device="cuda")).numel() == 0
+    f = _local_maxwellians(91, 2, 64, 3)
+    q1 = _eval(plan, f[:1])
+    assert per_cell_rel_linf(q1, oracle_near(plan, f[:1]), 64 * 64).max() <= TOL
+    p5 = gpu_lib.Plan(2, 64, 8.0, ntilde=5, dirs=[[0, 1], [1, 0], [1, 7], [2, 3]], mode=NEAR)
+    assert p5.ntilde == 5
+    q5 = _eval(p5, f)
+    errs = per_cell_rel_linf(q5, oracle_near(p5, f), 64 * 64)
+    print("n=64 ntilde=5 explicit lines: max cell rel err %.3e" % errs.max())
+    assert errs.max() <= TOL
+    g = f.copy()
+    g[1, 20, 33] = np.nan
+    qn = _eval(plan, g)
+    assert np.all(np.isfinite(qn[0])) and np.all(np.isfinite(qn[2]))
+    assert np.isnan(qn[1]).any()
+    assert np.array_equal(qn[0], _eval(plan, f)[0])
