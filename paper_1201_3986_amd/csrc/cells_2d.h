@@ -313,13 +313,13 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
         float2 tg[N];
-        job2d_multiply<N, (N < 8 ? N : 8)>(tg, gh, J, dtab, atab, j);
+        job2d_multiply<N>(tg, gh, J, dtab, atab, j);
         inv2d<N, RV>(tg, xb, j);                 // line(g) + i plane(g)
         if constexpr (STAGE) {
 #pragma unroll
             for (int i = 0; i < N; ++i) bstore2(tg[i], rtg, it.vspec, i * RS2);
         }
-        job2d_multiply<N, (N < 8 ? N : 8)>(z, fh, J, dtab, atab, j);
+        job2d_multiply<N>(z, fh, J, dtab, atab, j);
         inv2d<N, RV>(z, xb, j);                  // line(f) + i plane(f)
         if constexpr (STAGE) {
             // the parked transform of g, read a chunk at a time before use
