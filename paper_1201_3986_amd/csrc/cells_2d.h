@@ -357,6 +357,15 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
     }
 }
 
+// A double that is the same in every lane of the wave, moved to scalar registers.
+__device__ __forceinline__ double uniform(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 // The near-equilibrium evaluation with two waves per cell, for n = 64, where
 // one pencil fills half of a lane's registers: a wave that held both transforms
 // of a job and the accumulator ran at one wave per SIMD.  Here the g wave forms
@@ -368,15 +377,6 @@ __device__ __forceinline__ void cell2d_eval_split(const DevPlan& pl, const Item2
 // so that each wave hands the other only its plane field, through its own
 // slot.  The f wave's accumulator joins the g wave's at the end, which writes
 // the result.  All waves of the workgroup run the same number of cells.
-// A double that is the same in every lane of the wave, moved to scalar registers.
-__device__ __forceinline__ double uniform(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
-    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-
 template <int N, int RV>
 __device__ __forceinline__ void cell2d_eval_split_pair(const DevPlan& pl, const Item2D& it, rsrc_t rgh,
                                                        rsrc_t rlam, const float* __restrict__ jobw, float dt,
