@@ -192,8 +192,8 @@ def adaptive_step(qdvm, workloads, torch, args):
 
 def profile_workload(args, qdvm, workloads, torch):
     """One secondary workload alone: 3D n=32 P=16 on 2048 cells, its adjoint on
-    the 64-cell differentiation batch, the near-equilibrium mode on 16384 2D
-    n=64 cells, or the captured batched Euler step."""
+    the 64-cell differentiation batch, the adjoint and the near-equilibrium
+    mode on 16384 2D n=64 cells, or the captured batched Euler step."""
     if args.profile_workload == "3d_n32_p16":
         base3 = workloads.three_gaussians_batch(303, 64, 32)
         f3 = torch.from_numpy(np.ascontiguousarray(np.tile(base3, (32, 1, 1, 1)))).cuda()
@@ -208,6 +208,13 @@ def profile_workload(args, qdvm, workloads, torch):
         pl = qdvm.Plan(3, 32, 8.0, num_dirs=16)
         t = time_calls(lambda: pl.vjp(fv, cv), args.steps, args.warmup)
         print(json.dumps({"workload": "adjoint 3D n=32 P=16, 64 cells", "ms": t}), flush=True)
+    elif args.profile_workload == "vjp_2d_n64_p16":
+        base = workloads.two_maxwellians_batch(202, 64, 64, noise=0.05)
+        f = torch.from_numpy(np.ascontiguousarray(np.tile(base, (256, 1, 1)))).cuda()
+        cot = torch.from_numpy(np.random.default_rng(106).standard_normal(f.shape).astype(np.float32)).cuda()
+        pl = qdvm.Plan(2, 64, 8.0, num_dirs=16)
+        t = time_calls(lambda: pl.vjp(f, cot), args.steps, args.warmup)
+        print(json.dumps({"workload": "adjoint 2D n=64 P=16, 16384 cells", "ms": t}), flush=True)
     elif args.profile_workload == "near_2d_n64_p16":
         base = workloads.two_maxwellians_batch(202, 64, 64, noise=0.05)
         f = torch.from_numpy(np.ascontiguousarray(np.tile(base, (256, 1, 1)))).cuda()
@@ -231,7 +238,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB elementwise copy (x*1 -> y) to scale HBM counters")
-    ap.add_argument("--profile-workload", choices=["3d_n32_p16", "vjp_3d_n32_p16", "near_2d_n64_p16", "c4_step"],
+    ap.add_argument("--profile-workload",
+                    choices=["3d_n32_p16", "vjp_3d_n32_p16", "vjp_2d_n64_p16", "near_2d_n64_p16", "c4_step"],
                     default=None,
                     help="run only this secondary workload's timed loop (for counter collection) and exit")
     args = ap.parse_args()
