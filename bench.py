@@ -106,6 +106,21 @@ def step_percentiles(fn, steps):
     return [float(np.percentile(t, p)) for p in (10, 50, 90)]
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host (for the oracle timing)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
 def sampled_error(plan, f_np, q_np, idx):
     import oracle
     w = np.float32(plan.weights).astype(np.float64)
@@ -388,7 +403,8 @@ def main():
         dt = time.perf_counter() - t0
         cpu = {"value": cells / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": "%d cells of the headline workload (2D n=64, P=16), FP64 direct pair sum, "
-                         "%.1f s wall, OpenMP threads=%d" % (cells, dt, threads)}
+                         "%.1f s wall, OpenMP threads=%d" % (cells, dt, threads),
+               "host": host_cpu()}
         log("cpu oracle: %.2f cells/s on %d threads" % (cells / dt, threads))
 
     out = {
