@@ -323,6 +323,17 @@ def main():
             results["2d_n64_P%d" % P] = {"cells_per_s": B / (t * 1e-3), "ms": t, "rel_err": e,
                                          "tflops": algorithmic_flops(2, 64, pl.num_jobs) * B / (t * 1e-3) / 1e12}
             pl.close()
+        # the whole line sets of Farey order 8 (88 lines) and 14 (every line of the
+        # box at Nt = 14: 256 lines), the two extra points of the 2D n = 64 sweep
+        for order in (8, 14):
+            pl = qdvm.Plan(2, 64, 8.0, farey_order=order)
+            t = time_calls(lambda: pl.eval(f, out=q), 5, 1)
+            e = sampled_error(pl, f_np, q.cpu().numpy(), [0])
+            results["2d_n64_order%d" % order] = {
+                "lines": pl.num_dirs, "cells_per_s": B / (t * 1e-3), "ms": t, "rel_err": e,
+                "tflops": algorithmic_flops(2, 64, pl.num_jobs) * B / (t * 1e-3) / 1e12}
+            log("2D n=64 Farey order %d (%d lines): %.3f ms, rel err %.2e" % (order, pl.num_dirs, t, e))
+            pl.close()
         results["2d_n64_P16"] = {"cells_per_s": value, "ms": ms, "rel_err": err, "tflops": achieved}
         # PCIe-inclusive rate: f from pinned host memory, Q back to pinned host memory
         fh = torch.empty(f.shape, dtype=torch.float32, pin_memory=True)
