@@ -121,14 +121,25 @@ def host_cpu():
             "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
-def sampled_error(plan, f_np, q_np, idx):
+def cell_errors(plan, f_np, q_np, idx, near_equilibrium_definition=False):
+    """Relative L-infinity error of each listed cell against the FP64 oracle
+    (Q(f, f); or Q(f, f) - Q(M, M), the near-equilibrium mode's definition)."""
     import oracle
     w = np.float32(plan.weights).astype(np.float64)
-    errs = []
-    for c in idx:
-        ref = oracle.collide(plan.dim, plan.n, plan.ntilde, plan.dirs, w, f_np[c].astype(np.float64))
-        errs.append(float(np.max(np.abs(q_np[c].reshape(-1) - ref.reshape(-1))) / np.max(np.abs(ref))))
-    return max(errs)
+    idx = list(idx)
+    cells = np.stack([np.asarray(f_np[c], np.float32).astype(np.float64).reshape((plan.n,) * plan.dim)
+                      for c in idx])
+    if near_equilibrium_definition:
+        ref = oracle.collide_near_equilibrium(plan.dim, plan.n, plan.ntilde, plan.dirs, w, cells)
+    else:
+        ref = oracle.collide(plan.dim, plan.n, plan.ntilde, plan.dirs, w, cells)
+    ref = ref.reshape(len(idx), -1)
+    got = np.stack([np.asarray(q_np[c], np.float64).reshape(-1) for c in idx])
+    return np.max(np.abs(got - ref), axis=1) / np.max(np.abs(ref), axis=1)
+
+
+def sampled_error(plan, f_np, q_np, idx):
+    return float(np.max(cell_errors(plan, f_np, q_np, idx)))
 
 
 def batched_step(qdvm, workloads, torch, args):
@@ -161,10 +172,25 @@ def batched_step(qdvm, workloads, torch, args):
             p3.eval(y3, out=q3, dt=wl["dt"])
         ts = time_calls(single, max(5, args.steps // 2), 2)
         key = "c4_graph_step" + ("" if mode == "full" else "_near_equilibrium")
+        # Q of the initial state (dt = 0) on a seeded sample of cells against the oracle's Q(f, f)
+        qd = b.eval(torch.from_numpy(flat_np).cuda())
+        qn = qd.cpu().numpy()
+        rng = np.random.default_rng(4104)
+        s2 = np.sort(rng.choice(n2, size=256, replace=False))
+        s3 = np.sort(rng.choice(n3, size=16, replace=False))
+        e2 = cell_errors(p2, f2, qn[:n2 * 1024].reshape(n2, -1), s2)
+        e3 = cell_errors(p3, f3, qn[n2 * 1024:].reshape(n3, -1), s3)
+        rel = float(max(e2.max(), e3.max()))
         out[key] = {"ms": t, "cells_per_s": (n2 + n3) / (t * 1e-3), "tflops": b.flops / (t * 1e-3) / 1e12,
-                    "single_plan_launches_ms": ts, "batched_over_single": ts / t}
-        log("%s: %.3f ms per captured step (%.3e cells/s); single-plan launches %.3f ms"
-            % (key, t, (n2 + n3) / (t * 1e-3), ts))
+                    "single_plan_launches_ms": ts, "batched_over_single": ts / t,
+                    "rel_err_vs_Qff": rel, "rel_err_cells": "256 2D + 16 3D seeded cells",
+                    "meets_1e-5": rel <= 1e-5}
+        if mode == "full":
+            out[key]["note"] = ("plain FP32: gain and loss are 50-100x larger than Q on these near-equilibrium "
+                                "cells, so the plain mode does not meet 1e-5; the near-equilibrium step does")
+        log("%s: %.3f ms per captured step (%.3e cells/s); single-plan launches %.3f ms; rel err %.2e"
+            % (key, t, (n2 + n3) / (t * 1e-3), ts, rel))
+        del qd
         g.close()
         b.close()
         p2.close()
@@ -290,8 +316,14 @@ def main():
     flops = algorithmic_flops(2, 64, plan.num_jobs) * B
     achieved = flops / (ms * 1e-3) / 1e12
     q_np = q.cpu().numpy()
-    err = sampled_error(plan, f_np, q_np, [0, 1, 2, 3, B - 1])
-    log("headline: %.3f ms/step, %.3e cells/s, %.1f TFLOP/s, sampled rel err %.2e" % (ms, value, achieved, err))
+    # every distinct cell of the step against the oracle (the batch tiles 256 draws)
+    n_check = min(distinct, B)
+    head_errs = cell_errors(plan, f_np, q_np, range(n_check))
+    err = float(head_errs.max())
+    tiles_equal = all(np.array_equal(q_np[:n_check], q_np[t:t + n_check])
+                      for t in range(n_check, B - n_check + 1, n_check))
+    log("headline: %.3f ms/step, %.3e cells/s, %.1f TFLOP/s, rel err over %d distinct cells %.2e (cell %d)"
+        % (ms, value, achieved, n_check, err, int(np.argmax(head_errs))))
     traffic = recorded_traffic("eval2d_n64_p16_traffic.md")
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -319,8 +351,9 @@ def main():
         for P in (8, 32):
             pl = qdvm.Plan(2, 64, 8.0, num_dirs=P)
             t = time_calls(lambda: pl.eval(f, out=q), max(5, args.steps // 4), 2)
-            e = sampled_error(pl, f_np, q.cpu().numpy(), [0, 5])
+            e = sampled_error(pl, f_np, q.cpu().numpy(), range(n_check))
             results["2d_n64_P%d" % P] = {"cells_per_s": B / (t * 1e-3), "ms": t, "rel_err": e,
+                                         "rel_err_cells": n_check,
                                          "tflops": algorithmic_flops(2, 64, pl.num_jobs) * B / (t * 1e-3) / 1e12}
             pl.close()
         # the whole line sets of Farey order 8 (88 lines) and 14 (every line of the
@@ -328,13 +361,15 @@ def main():
         for order in (8, 14):
             pl = qdvm.Plan(2, 64, 8.0, farey_order=order)
             t = time_calls(lambda: pl.eval(f, out=q), 5, 1)
-            e = sampled_error(pl, f_np, q.cpu().numpy(), [0])
+            e = sampled_error(pl, f_np, q.cpu().numpy(), range(0, n_check, 4))
             results["2d_n64_order%d" % order] = {
                 "lines": pl.num_dirs, "cells_per_s": B / (t * 1e-3), "ms": t, "rel_err": e,
+                "rel_err_cells": len(range(0, n_check, 4)),
                 "tflops": algorithmic_flops(2, 64, pl.num_jobs) * B / (t * 1e-3) / 1e12}
             log("2D n=64 Farey order %d (%d lines): %.3f ms, rel err %.2e" % (order, pl.num_dirs, t, e))
             pl.close()
-        results["2d_n64_P16"] = {"cells_per_s": value, "ms": ms, "rel_err": err, "tflops": achieved}
+        results["2d_n64_P16"] = {"cells_per_s": value, "ms": ms, "rel_err": err, "rel_err_cells": n_check,
+                                 "tflops": achieved}
         # PCIe-inclusive rate: f from pinned host memory, Q back to pinned host memory
         fh = torch.empty(f.shape, dtype=torch.float32, pin_memory=True)
         fh.copy_(torch.from_numpy(f_np))
@@ -352,9 +387,16 @@ def main():
         # the same cells in the near-equilibrium mode (rel err against the oracle's Q(f, f))
         pn = qdvm.Plan(2, 64, 8.0, num_dirs=16, mode="near_equilibrium")
         t = time_calls(lambda: pn.eval(f, out=q), max(5, args.steps // 4), 2)
-        e = sampled_error(pn, f_np, q.cpu().numpy(), [0, 5])
-        results["2d_n64_P16_near_equilibrium"] = {"cells_per_s": B / (t * 1e-3), "ms": t, "rel_err_vs_Qff": e}
-        log("near-equilibrium 2D n=64 P=16: %.3f ms, rel err %.2e" % (t, e))
+        qn = q.cpu().numpy()
+        e_ff = cell_errors(pn, f_np, qn, range(n_check))
+        e_def = cell_errors(pn, f_np, qn, range(n_check), near_equilibrium_definition=True)
+        results["2d_n64_P16_near_equilibrium"] = {
+            "cells_per_s": B / (t * 1e-3), "ms": t, "rel_err_vs_definition": float(e_def.max()),
+            "rel_err_vs_Qff": float(e_ff.max()), "cells_checked": n_check,
+            "note": "the mode returns Q(f,f) - Q(M,M); on these two-Maxwellian cells the fitted M is wide and "
+                    "its periodic-wrap residue Q(M,M) is not negligible, so it is not an evaluation of Q(f,f) here"}
+        log("near-equilibrium 2D n=64 P=16: %.3f ms, rel err vs definition %.2e, vs Q(f,f) %.2e"
+            % (t, e_def.max(), e_ff.max()))
         pn.close()
         # 2D adjoint on the headline cells (same f, a N(0,1) cotangent)
         cot = torch.from_numpy(np.random.default_rng(106).standard_normal(f.shape).astype(np.float32)).cuda()
@@ -376,9 +418,10 @@ def main():
         for P in (8, 16):
             pl = qdvm.Plan(3, 32, 8.0, num_dirs=P)
             t = time_calls(lambda: pl.eval(f3, out=q3), max(5, args.steps // 5), 2)
-            e = sampled_error(pl, f3_np, q3.cpu().numpy(), [1])
+            e = sampled_error(pl, f3_np, q3.cpu().numpy(), [1, 22, 45, 63])
             ev3[P] = t
             results["3d_n32_P%d" % P] = {"cells_per_s": C3 / (t * 1e-3), "ms": t, "rel_err": e,
+                                         "rel_err_cells": 4,
                                          "tflops": algorithmic_flops(3, 32, pl.num_jobs) * C3 / (t * 1e-3) / 1e12}
             log("3D n=32 P=%d: %.3f ms for %d cells, rel err %.2e" % (P, t, C3, e))
             if P == 16:
@@ -436,7 +479,9 @@ def main():
                    "dim": 2, "n": 64, "half_width": 8.0, "ntilde": plan.ntilde, "num_dirs": 16,
                    "cells_per_step": B, "parallelism": "single GPU"},
         "step_ms_p10_p50_p90": pct,
-        "parity": {"rel_linf_sampled": err, "tolerance": 1e-5},
+        "parity": {"rel_linf": err, "cells_checked": n_check, "distinct_cells_in_step": n_check,
+                   "median_cell_rel_linf": float(np.median(head_errs)), "tolerance": 1e-5,
+                   "meets_tolerance": err <= 1e-5, "tiles_bit_identical": bool(tiles_equal)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "results": results,

@@ -26,10 +26,13 @@
  *     default stream).  Errors detected on the host are returned at once and
  *     nothing is launched or written; faults inside kernels surface as
  *     QDVM_EDEVICE from a later synchronising call.
- *   - A plan's device workspace is shared by all calls on that plan: calls on
- *     one plan must be ordered (one stream, or externally serialised).
- *     Different plans are independent.  Plans are bound to the device that
- *     was current at creation; calls must be made with that device current.
+ *   - A plan's device workspace is allocated with the plan, sized for every
+ *     batch size, and shared by all calls on that plan: qdvm_eval and qdvm_vjp
+ *     never allocate, free or synchronise (they may be captured into a HIP
+ *     graph), and calls on one plan must be ordered (one stream, or externally
+ *     serialised).  Different plans are independent.  Plans are bound to the
+ *     device that was current at creation; calls must be made with that
+ *     device current.
  *   - No exception crosses this interface.
  */
 #ifndef QDVM_H
@@ -106,9 +109,12 @@ typedef struct {
 } qdvm_plan_info_t;
 
 /* Build a plan: direction set, line lengths M_p, weights and FP64-built
- * multiplier tables, uploaded to the current device.  *out is written only on
- * success.  EINVAL for an invalid descriptor, EUNSUPPORTED for n outside the
- * supported set, ENOMEM/EDEVICE for device failures. */
+ * multiplier tables, uploaded to the current device, and the workspace of
+ * every later evaluation and adjoint call (spectral scratch for the resident
+ * cells of the largest launch; tens to a few hundred MiB depending on the
+ * grid).  Synchronises the device.  *out is written only on success.
+ * EINVAL for an invalid descriptor, EUNSUPPORTED for n outside the supported
+ * set, ENOMEM/EDEVICE for device failures. */
 qdvm_status qdvm_plan(const qdvm_desc* desc, qdvm_plan_t* out);
 
 /* Destroy a plan.  Synchronises the device (work on any stream may still read

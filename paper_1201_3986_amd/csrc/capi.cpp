@@ -135,19 +135,21 @@ qdvm_status check_device(const qdvm_plan_s* p)
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Workspace layout for one call: lam | jobw | spec | spec2 | acc | gw_part.
+// Workspace layout for one call: lam | jobw | spec | spec2 | acc | gw_part | part.
 struct WsLayout {
     size_t lam, jobw, spec, spec2, acc, gw, part, total;
 };
 
-WsLayout ws_layout(const qdvm::HostPlan& hp, const qdvm::LaunchInfo& li, int batch, bool adjoint)
+// slots: resident cell slots of the launch; rows: grad_w partial rows;
+// part_cells: workgroups of a direction-split launch (0 if none).
+WsLayout ws_layout(const qdvm::HostPlan& hp, size_t slots, size_t rows, size_t part_cells, bool adjoint)
 {
     WsLayout L{};
-    const int slots = li.slots;
     const size_t npts = (size_t)hp.npts();
+    const size_t njobs = std::max<size_t>(1, hp.jobs.size());
     size_t off = 0;
     L.lam = off; off = align_up(off + sizeof(float) * npts);
-    L.jobw = off; off = align_up(off + sizeof(float) * std::max<size_t>(1, hp.jobs.size()));
+    L.jobw = off; off = align_up(off + sizeof(float) * njobs);
     L.spec = off; off = align_up(off + sizeof(float2) * npts * slots);
     if (adjoint || hp.mode) {
         // adjoint: one slot set; near-equilibrium evaluation: g and a staging set
@@ -155,40 +157,41 @@ WsLayout ws_layout(const qdvm::HostPlan& hp, const qdvm::LaunchInfo& li, int bat
     }
     if (adjoint) {
         L.acc = off; off = align_up(off + sizeof(float2) * npts * slots);
-        L.gw = off; off = align_up(off + sizeof(float) * std::max<size_t>(1, hp.jobs.size()) * batch);
+        L.gw = off; off = align_up(off + sizeof(double) * njobs * rows);
     }
-    if (li.jsplit > 1) {
-        L.part = off; off = align_up(off + sizeof(float) * npts * (size_t)batch * li.jsplit);
+    if (part_cells) {
+        L.part = off; off = align_up(off + sizeof(float) * npts * part_cells);
     }
     L.total = off;
     return L;
 }
 
-qdvm_status ensure_ws(qdvm::HostPlan& hp, size_t bytes, hipStream_t st)
+WsLayout call_layout(const qdvm::HostPlan& hp, const qdvm::LaunchInfo& li, int batch, bool adjoint)
 {
-    if (hp.ws_bytes >= bytes) return QDVM_OK;
-    if (hp.d_ws) {
-        // the previous buffer may still be read by work queued on any stream
-        (void)st;
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return from_hip(e, "synchronising before workspace growth");
-        hipFree(hp.d_ws);
-        hp.d_ws = nullptr;
-        hp.ws_bytes = 0;
-    }
-    size_t want = bytes + bytes / 4;
-    hipError_t e = hipMalloc(&hp.d_ws, want);
-    if (e != hipSuccess) {
-        hp.d_ws = nullptr;
-        return from_hip(e, "allocating the plan workspace");
-    }
-    hp.ws_bytes = want;
+    const size_t slots = (size_t)li.slots;
+    return ws_layout(hp, slots, std::min<size_t>((size_t)batch, slots), li.jsplit > 1 ? (size_t)li.grid : 0,
+                     adjoint);
+}
+
+// Workspace that serves every batch size, variant and operation of a plan:
+// the layout at the largest number of resident slots any launch can use.
+qdvm_status workspace_bound(const qdvm::HostPlan& hp, size_t& bytes)
+{
+    const qdvm::DevPlan pl = hp.dev();
+    bytes = 0;
+    for (int op = 0; op < 2; ++op)
+        for (int v = 0; v < qdvm::num_variants(hp.dim, hp.n); ++v) {
+            const int slots = qdvm::max_slots(pl, op, v);
+            if (slots <= 0) return fail(QDVM_EDEVICE, "could not size the plan workspace (occupancy query failed)");
+            const WsLayout L = ws_layout(hp, (size_t)slots, (size_t)slots, hp.dim == 3 ? (size_t)slots : 0, op == 1);
+            bytes = std::max(bytes, L.total);
+        }
     return QDVM_OK;
 }
 
-qdvm::DevScratch scratch_of(const qdvm::HostPlan& hp, const WsLayout& L, bool adjoint, int jsplit)
+qdvm::DevScratch scratch_of(void* base, const qdvm::HostPlan& hp, const WsLayout& L, bool adjoint, int jsplit)
 {
-    char* b = (char*)hp.d_ws;
+    char* b = (char*)base;
     qdvm::DevScratch s{};
     s.lam = (float*)(b + L.lam);
     s.jobw = (float*)(b + L.jobw);
@@ -196,7 +199,7 @@ qdvm::DevScratch scratch_of(const qdvm::HostPlan& hp, const WsLayout& L, bool ad
     if (adjoint || hp.mode) s.spec2 = (float2*)(b + L.spec2);
     if (adjoint) {
         s.acc = (float2*)(b + L.acc);
-        s.gw_part = (float*)(b + L.gw);
+        s.gw_part = (double*)(b + L.gw);
     }
     if (jsplit > 1) s.part = (float*)(b + L.part);
     return s;
@@ -214,10 +217,9 @@ qdvm_status do_eval(qdvm_plan_s* p, int batch, const float* f, float* q, const f
     const qdvm::DevPlan pl = hp.dev();
     qdvm::LaunchInfo li = qdvm::eval_launch_info(pl, batch, variant);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
-    WsLayout L = ws_layout(hp, li, batch, false);
-    qdvm_status s = ensure_ws(hp, L.total, st);
-    if (s != QDVM_OK) return s;
-    qdvm::DevScratch sc = scratch_of(hp, L, false, li.jsplit);
+    const WsLayout L = call_layout(hp, li, batch, false);
+    if (L.total > hp.ws_bytes) return fail(QDVM_EDEVICE, "internal: launch needs more than the plan workspace");
+    qdvm::DevScratch sc = scratch_of(hp.d_ws, hp, L, false, li.jsplit);
     hipError_t e = hipSuccess;
     if (w) {
         e = qdvm::launch_prep(pl, w, sc, st);
@@ -228,7 +230,6 @@ qdvm_status do_eval(qdvm_plan_s* p, int batch, const float* f, float* q, const f
     }
     e = qdvm::launch_eval(pl, batch, f, q, dt, sc, li, variant, st);
     if (e != hipSuccess) return from_hip(e, "launching the collision kernel");
-    hp.last_stream = st;
     return QDVM_OK;
 }
 
@@ -239,10 +240,9 @@ qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, co
     const qdvm::DevPlan pl = hp.dev();
     qdvm::LaunchInfo li = qdvm::vjp_launch_info(pl, batch, variant);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the adjoint kernel");
-    WsLayout L = ws_layout(hp, li, batch, true);
-    qdvm_status s = ensure_ws(hp, L.total, st);
-    if (s != QDVM_OK) return s;
-    qdvm::DevScratch sc = scratch_of(hp, L, true, li.jsplit);
+    const WsLayout L = call_layout(hp, li, batch, true);
+    if (L.total > hp.ws_bytes) return fail(QDVM_EDEVICE, "internal: launch needs more than the plan workspace");
+    qdvm::DevScratch sc = scratch_of(hp.d_ws, hp, L, true, li.jsplit);
     hipError_t e = hipSuccess;
     if (w) {
         e = qdvm::launch_prep(pl, w, sc, st);
@@ -253,7 +253,6 @@ qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, co
     }
     e = qdvm::launch_vjp(pl, batch, f, c, gf, gw, w ? w : hp.d_w, sc, li, variant, st);
     if (e != hipSuccess) return from_hip(e, "launching the adjoint kernel");
-    hp.last_stream = st;
     return QDVM_OK;
 }
 
@@ -362,6 +361,21 @@ qdvm_status qdvm_plan(const qdvm_desc* desc, qdvm_plan_t* out)
         free_device(hp);
         delete p;
         return from_hip(e, "uploading plan tables");
+    }
+    // the workspace of every later call, sized once for any batch
+    size_t ws = 0;
+    qdvm_status wst = workspace_bound(hp, ws);
+    if (wst == QDVM_OK) {
+        e = hipMalloc(&hp.d_ws, ws);
+        if (e == hipSuccess)
+            hp.ws_bytes = ws;
+        else
+            wst = from_hip(e, "allocating the plan workspace");
+    }
+    if (wst != QDVM_OK) {
+        free_device(hp);
+        delete p;
+        return wst;
     }
     *out = p;
     return QDVM_OK;

@@ -555,8 +555,8 @@ __device__ __forceinline__ void cell2d_eval_split_pair(const DevPlan& pl, const 
 template <int N, int RV>
 __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, rsrc_t rc, rsrc_t rr,
                                            rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
-                                           float* __restrict__ gwp, bool valid, float inv_n2, float inv_n,
-                                           float* xb, const float* dtab, int j)
+                                           double* __restrict__ gwp, bool gw_first, bool valid, float inv_n2,
+                                           float inv_n, float* xb, const float* dtab, int j)
 {
     constexpr int RS = N * 4, RS2 = N * 8;
     const int mrow = (N - j) & (N - 1);                          // mirror row
@@ -643,7 +643,7 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
             }
         }
         const float tot = group_sum<N>(rpart * inv_n2 - spart * inv_n);
-        if (j == 0 && valid) gwp[jb] = tot;
+        if (j == 0 && valid) gw_accumulate(gwp + jb, tot, gw_first);
         fwd2d<N, RV>(z, xb, j);
         {
             // the multipliers are read again rather than kept from the first

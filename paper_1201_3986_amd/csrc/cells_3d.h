@@ -565,9 +565,9 @@ __device__ __forceinline__ void mirror_exchange(const float2 (&z)[Q][N], float2 
 template <int N, int T, int RV>
 __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, rsrc_t rc, rsrc_t rr,
                                            rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
-                                           float* __restrict__ gwp, float inv_n2, float inv_n, float* xb,
-                                           float* red, const float* dtab, int tid, int jb0 = 0, int jstep = 1,
-                                           bool loss = true)
+                                           double* __restrict__ gwp, bool gw_first, float inv_n2, float inv_n,
+                                           float* xb, float* red, const float* dtab, int tid, int jb0 = 0,
+                                           int jstep = 1, bool loss = true)
 {
     constexpr int NN = N * N, Q = NN / T, RS = NN * 4, RS2 = NN * 8;
     float2 z[Q][N];
@@ -685,7 +685,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
             }
         }
         const float tot = block_sum<N, T, Q>(rpart * inv_n2 - spart * inv_n, red, tid);
-        if (tid == 0) gwp[jb] = tot;
+        if (tid == 0) gw_accumulate(gwp + jb, tot, gw_first);
         fwd3d<N, T, Q, RV>(z, xb, tid);
         // Only the Hermitian part of (a - i a') uhat reaches Re IFFT(S), so S is
         // kept as that part, in half pencils: it needs uhat(-K), held by the

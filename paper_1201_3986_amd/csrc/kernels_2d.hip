@@ -129,7 +129,9 @@ __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const floa
         it.f = make_rsrc(f + (size_t)first * NPTS, nvalid * NPTS * 4);
         it.q = make_rsrc(g + (size_t)first * NPTS, nvalid * NPTS * 4);
         const rsrc_t rc = make_rsrc(c + (size_t)first * NPTS, nvalid * NPTS * 4);
-        cell2d_vjp<N, RV>(pl, it, rc, rr, rsh, rlam, s.jobw, s.gw_part + (size_t)(valid ? cell : 0) * pl.njobs,
+        // grad_w partials: row blockIdx * CPB + local accumulates this slot's cells
+        cell2d_vjp<N, RV>(pl, it, rc, rr, rsh, rlam, s.jobw,
+                          s.gw_part + ((size_t)blockIdx.x * CPB + local) * pl.njobs, item == (int)blockIdx.x,
                           valid, inv_n2, inv_n, xb, dtab, j);
     }
 }
@@ -149,7 +151,7 @@ size_t lds2d(int ntilde) { return sizeof(float) * ((size_t)(256 / N) * N * (N + 
         default: return hipErrorInvalidValue;              \
     }
 
-hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li)
+hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid)
 {
     hipError_t e = hipSuccess;
     QDVM_SWITCH_2D(pl.n, {
@@ -161,6 +163,7 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
             li.lds = sizeof(float) * ((size_t)2 * N * (N + 1) + (size_t)2 * (pl.ntilde + 1) * N);
             e = variant ? occupancy_grid(k_eval2d_pair<1>, 128, li.lds, batch, li.grid)
                         : occupancy_grid(k_eval2d_pair<0>, 128, li.lds, batch, li.grid);
+            if (max_grid > 0) li.grid = std::min(li.grid, max_grid);
             li.slots = li.grid;
             return e;
         }
@@ -170,6 +173,7 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
         else
             e = variant ? occupancy_grid(k_eval2d<N, 1, false>, 256, li.lds, items, li.grid)
                         : occupancy_grid(k_eval2d<N, 0, false>, 256, li.lds, items, li.grid);
+        if (max_grid > 0) li.grid = std::min(li.grid, max_grid);
         li.slots = li.grid * (256 / N);
     });
     return e;
@@ -194,7 +198,7 @@ hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q,
     return hipGetLastError();
 }
 
-hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li)
+hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid)
 {
     hipError_t e = hipSuccess;
     QDVM_SWITCH_2D(pl.n, {
@@ -203,6 +207,7 @@ hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li)
         const int items = (batch + 256 / N - 1) / (256 / N);
         e = variant ? occupancy_grid(k_vjp2d<N, 1>, 256, li.lds, items, li.grid)
                     : occupancy_grid(k_vjp2d<N, 0>, 256, li.lds, items, li.grid);
+        if (max_grid > 0) li.grid = std::min(li.grid, max_grid);
         li.slots = li.grid * (256 / N);
     });
     return e;

@@ -94,8 +94,9 @@ __global__ __launch_bounds__(T) void k_vjp3d(DevPlan pl, int batch, const float*
         cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
         cl.q = make_rsrc(g + (size_t)cell * NPTS, NPTS * 4);
         const rsrc_t rc = make_rsrc(c + (size_t)cell * NPTS, NPTS * 4);
-        cell3d_vjp<N, T, RV>(pl, cl, rc, rr, rsh, rlam, s.jobw, s.gw_part + (size_t)cell * pl.njobs, inv_n2,
-                             inv_n, xb, red, dtab, tid);
+        // grad_w partials: row blockIdx accumulates this workgroup's cells
+        cell3d_vjp<N, T, RV>(pl, cl, rc, rr, rsh, rlam, s.jobw, s.gw_part + (size_t)blockIdx.x * pl.njobs,
+                             cell == (int)blockIdx.x, inv_n2, inv_n, xb, red, dtab, tid);
     }
 }
 
@@ -145,8 +146,8 @@ __global__ __launch_bounds__(T) void k_vjp3d_js(DevPlan pl, int batch, int G, co
     cl.fh = make_rsrc(s.spec + slot, NPTS * 8);
     cell3d_vjp<N, T, RV>(pl, cl, make_rsrc(c + (size_t)cell * NPTS, NPTS * 4), make_rsrc(s.spec2 + slot, NPTS * 8),
                          make_rsrc(s.acc + slot, NPTS * 8), make_rsrc(s.lam, NPTS * 4), s.jobw,
-                         s.gw_part + (size_t)cell * pl.njobs, inv_n * inv_n, inv_n, xb, red, dtab, tid, g, G,
-                         g == 0);
+                         s.gw_part + (size_t)cell * pl.njobs, true, inv_n * inv_n, inv_n, xb, red, dtab, tid, g,
+                         G, g == 0);
 }
 
 // out = sum_g part[g] (g ascending), or f + dt * sum when dt != 0; out may equal f.
@@ -208,18 +209,18 @@ __global__ void k_prep(DevPlan pl, const float* __restrict__ w, float* __restric
     lam[idx] = (float)(acc * inv);
 }
 
-// grad_w[p] = sum over cells of the job partial of the job holding p (0 if none),
-// in FP64: one workgroup per direction, thread t summing cells t, t + 256, ...,
+// grad_w[p] = sum over the partial rows of the job holding p (0 if none), in
+// FP64: one workgroup per direction, thread t summing rows t, t + 256, ...,
 // then a fixed tree over the threads (the order does not depend on timing).
-__global__ __launch_bounds__(256) void k_gw_reduce(DevPlan pl, int batch, const int32_t* __restrict__ dir_job,
-                                                   const float* __restrict__ part, float* __restrict__ gw)
+__global__ __launch_bounds__(256) void k_gw_reduce(DevPlan pl, int rows, const int32_t* __restrict__ dir_job,
+                                                   const double* __restrict__ part, float* __restrict__ gw)
 {
     __shared__ double red[256];
     const int p = blockIdx.x, tid = threadIdx.x;
     const int jb = dir_job[p];
     double acc = 0.0;
     if (jb >= 0)
-        for (int c = tid; c < batch; c += 256) acc += (double)part[(size_t)c * pl.njobs + jb];
+        for (int c = tid; c < rows; c += 256) acc += part[(size_t)c * pl.njobs + jb];
     red[tid] = acc;
     __syncthreads();
     for (int o = 128; o >= 1; o >>= 1) {
@@ -295,12 +296,12 @@ hipError_t launch_prep(const DevPlan& pl, const float* w, DevScratch s, hipStrea
     return hipGetLastError();
 }
 
-LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant)
+LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim)
 {
     LaunchInfo li;
     hipError_t e = hipSuccess;
     if (pl.dim == 2) {
-        e = eval2d_info(pl, batch, variant, li);
+        e = eval2d_info(pl, batch, variant, li, lim.max_grid);
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
@@ -313,8 +314,9 @@ LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant)
                 else
                     e = variant ? occupancy_grid(k_eval3d<N, T, 1, false>, T, li.lds, batch, li.grid)
                                 : occupancy_grid(k_eval3d<N, T, 0, false>, T, li.lds, batch, li.grid);
+                if (lim.max_grid > 0) li.grid = std::min(li.grid, lim.max_grid);
                 li.slots = li.grid;
-                if (e == hipSuccess && !pl.mode) {
+                if (e == hipSuccess && !pl.mode && lim.allow_split) {
                     int cap = 0;
                     e = variant ? occupancy_grid(k_eval3d_js<N, T, 1>, T, li.lds, 1 << 30, cap)
                                 : occupancy_grid(k_eval3d_js<N, T, 0>, T, li.lds, 1 << 30, cap);
@@ -353,12 +355,12 @@ hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, f
     return hipGetLastError();
 }
 
-LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant)
+LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim)
 {
     LaunchInfo li;
     hipError_t e = hipSuccess;
     if (pl.dim == 2) {
-        e = vjp2d_info(pl, batch, variant, li);
+        e = vjp2d_info(pl, batch, variant, li, lim.max_grid);
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
@@ -367,8 +369,9 @@ LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant)
                 li.lds = lds3d<N, T>(pl.ntilde);
                 e = variant ? occupancy_grid(k_vjp3d<N, T, 1>, T, li.lds, batch, li.grid)
                             : occupancy_grid(k_vjp3d<N, T, 0>, T, li.lds, batch, li.grid);
+                if (lim.max_grid > 0) li.grid = std::min(li.grid, lim.max_grid);
                 li.slots = li.grid;
-                if (e == hipSuccess) {
+                if (e == hipSuccess && lim.allow_split) {
                     int cap = 0;
                     e = variant ? occupancy_grid(k_vjp3d_js<N, T, 1>, T, li.lds, 1 << 30, cap)
                                 : occupancy_grid(k_vjp3d_js<N, T, 0>, T, li.lds, 1 << 30, cap);
@@ -381,6 +384,35 @@ LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant)
     }
     if (e != hipSuccess) li.grid = 0;
     return li;
+}
+
+int max_slots(const DevPlan& pl, int op, int variant)
+{
+    const int big = 1 << 28;
+    const LaunchInfo li = op == 0 ? eval_launch_info(pl, big, variant) : vjp_launch_info(pl, big, variant);
+    if (li.grid <= 0) return 0;
+    int slots = li.slots;
+    if (pl.dim == 3 && !(op == 0 && pl.mode)) {
+        // direction-split launches: one slot per workgroup, up to the split kernel's occupancy
+        int cap = 0;
+        hipError_t e = hipSuccess;
+        auto body = [&]() -> hipError_t {
+            QDVM_SWITCH_3D(pl.n, {
+                constexpr int T = t3d<N>();
+                const size_t lds = lds3d<N, T>(pl.ntilde);
+                if (op == 0)
+                    e = variant ? occupancy_grid(k_eval3d_js<N, T, 1>, T, lds, 1 << 30, cap)
+                                : occupancy_grid(k_eval3d_js<N, T, 0>, T, lds, 1 << 30, cap);
+                else
+                    e = variant ? occupancy_grid(k_vjp3d_js<N, T, 1>, T, lds, 1 << 30, cap)
+                                : occupancy_grid(k_vjp3d_js<N, T, 0>, T, lds, 1 << 30, cap);
+            });
+            return e;
+        };
+        if (body() != hipSuccess) return 0;
+        slots = std::max(slots, cap);
+    }
+    return slots;
 }
 
 hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
@@ -419,7 +451,11 @@ hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float*
     }
     if (e != hipSuccess) return e;
     if (grad_w) {
-        hipLaunchKernelGGL(k_gw_reduce, dim3(pl.P), dim3(256), 0, st, pl, batch, pl.dir_job, s.gw_part, grad_w);
+        // rows written: the slots that took a first cell (2D: row b * CPB + l
+        // holds cell b * CPB + l first; 3D: row b holds cell b), or one per
+        // cell in a direction-split launch (batch < slots there)
+        const int rows = std::min(batch, li.slots);
+        hipLaunchKernelGGL(k_gw_reduce, dim3(pl.P), dim3(256), 0, st, pl, rows, pl.dir_job, s.gw_part, grad_w);
         e = hipGetLastError();
     }
     return e;

@@ -181,6 +181,19 @@ __device__ __forceinline__ double opaque(double v)
     return v;
 }
 
+// grad_w partial of one job in a slot's FP64 row: the slot's first cell stores
+// it, later cells add to it.  One thread owns the row and its cells come in a
+// fixed order, so the sum is the same on every run; the add is an atomic
+// read-modify-write performed at the device-coherent cache level, which cannot
+// see a stale copy of the value this thread wrote before.
+__device__ __forceinline__ void gw_accumulate(double* p, float v, bool first)
+{
+    if (first)
+        *p = (double)v;
+    else
+        atomicAdd(p, (double)v);
+}
+
 template <int N>
 __device__ __forceinline__ int modc(int x)
 {

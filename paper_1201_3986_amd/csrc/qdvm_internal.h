@@ -40,7 +40,9 @@ struct DevScratch {
     float2* spec;    // [slots * npts] spectrum of f per resident cell slot
     float2* spec2;   // [slots * npts] second spectral buffer (adjoint; g in near-equilibrium mode)
     float2* acc;     // [slots * npts] spectral accumulator (adjoint)
-    float* gw_part;  // [batch * njobs] per-cell job partials of grad_w (adjoint)
+    double* gw_part; // [rows][njobs] FP64 job partials of grad_w (adjoint): one row per resident
+                     // slot, accumulating that slot's cells in launch order (persistent launches),
+                     // or one row per cell (direction-split launches); rows = min(batch, slots)
     float* part;     // [jsplit][batch][npts] per-workgroup parts of Q or grad_f (direction-split launches)
     int32_t* counter;  // work-queue counter (batched)
 };
@@ -64,10 +66,9 @@ struct HostPlan {
     float* d_jobw0 = nullptr;
     std::vector<int32_t> dir_job;    // P
     int device = 0;
-    // workspace (grown on demand)
+    // workspace, allocated with the plan and sized for every batch (max_slots)
     void* d_ws = nullptr;
     size_t ws_bytes = 0;
-    hipStream_t last_stream = nullptr;
     int npts() const { int t = 1; for (int a = 0; a < dim; ++a) t *= n; return t; }
     DevPlan dev() const
     {
@@ -99,20 +100,33 @@ struct LaunchInfo {
     int jsplit = 1;   // > 1: each cell's direction loop is spread over jsplit workgroups
 };
 
+// Launch shape limits: max_grid > 0 caps the number of workgroups (the
+// persistent kernels then take more cells per workgroup); allow_split = false
+// keeps one workgroup per cell even for small 3D batches.
+struct LaunchLimits {
+    int max_grid = 0;
+    bool allow_split = true;
+};
+
 hipError_t launch_prep(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st);
-LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant);
+LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim = LaunchLimits());
 hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, float dt,
                        DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
-LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant);
+LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim = LaunchLimits());
+// Largest number of resident cell slots any batch can use with the kernels of
+// op (0: evaluation, 1: adjoint) and variant, direction-split launches
+// included: it bounds the spectral scratch, the grad_w partial rows and the
+// split parts, so a plan's workspace can be sized once for every batch.
+int max_slots(const DevPlan& pl, int op, int variant);
 hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
                       float* grad_w, const float* w, DevScratch s, const LaunchInfo& li, int variant,
                       hipStream_t st);
 
 // 2D launchers (kernels_2d.hip), called by the dispatch in kernels_3d.hip.
-hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li);
+hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid);
 hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q, float dt, DevScratch s,
                          const LaunchInfo& li, int variant, hipStream_t st);
-hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li);
+hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid);
 hipError_t launch_vjp2d(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
                         DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
 

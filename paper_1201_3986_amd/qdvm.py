@@ -162,6 +162,10 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib.qdvm_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
+        # what the caller asked for (explicit lists or the defaults the library fills in)
+        self.request = dict(half_width=float(half_width), ntilde=int(ntilde), farey_order=int(farey_order),
+                            num_dirs=int(num_dirs), explicit_dirs=dirs is not None,
+                            explicit_weights=weights is not None)
         info = PlanInfo()
         _check(lib.qdvm_plan_info(h, ctypes.byref(info)))
         self.dim, self.n, self.ntilde = info.dim, info.n, info.ntilde
@@ -405,9 +409,11 @@ def _make_function():
         @staticmethod
         def forward(ctx, f, w, plan):
             ctx.plan = plan
+            f = f.contiguous()
+            w = w.contiguous() if w is not None else None
             ctx.save_for_backward(f, w if w is not None else torch.empty(0, device=f.device))
             ctx.has_w = w is not None
-            return plan.eval(f.contiguous(), w=w)
+            return plan.eval(f, w=w)
 
         @staticmethod
         def backward(ctx, grad_out):

@@ -6,18 +6,54 @@ import numpy as np
 import oracle
 
 
+def assert_oracle_direction_set(plan):
+    """The set a GPU test checks must be the oracle's own: where the plan took
+    the library's defaults (first P lines, every line of a Farey order, default
+    weights, default Nt), its lists must equal the oracle's enumeration, so a
+    regression in the product's plan builder cannot pass a parity test by
+    handing the oracle the same wrong set."""
+    r = getattr(plan, "request", None)
+    assert r is not None, "plan without its request record"
+    if r["ntilde"] == 0:
+        assert plan.ntilde == oracle.default_ntilde(plan.n), (plan.ntilde, plan.n)
+    if not r["explicit_dirs"]:
+        ref = oracle.first_lines(plan.dim, r["num_dirs"]) if r["num_dirs"] > 0 \
+            else oracle.lines(plan.dim, r["farey_order"])
+        assert np.array_equal(np.asarray(plan.dirs), ref), "plan directions differ from the oracle's"
+    if not r["explicit_weights"]:
+        h = 2.0 * r["half_width"] / plan.n
+        ref_w = oracle.default_weights(plan.dim, h, plan.dirs)
+        assert np.allclose(plan.weights, ref_w, rtol=1e-14, atol=0.0), "plan weights differ from the oracle's"
+
+
 def oracle_q(plan, f32, w=None):
     """Oracle Q for the cells of f32 (numpy float32, batch * n^d) under `plan`."""
+    assert_oracle_direction_set(plan)
     weights = np.float32(plan.weights if w is None else w).astype(np.float64)
     f64 = np.asarray(f32, dtype=np.float32).astype(np.float64)
     return oracle.collide(plan.dim, plan.n, plan.ntilde, plan.dirs, weights, f64)
 
 
 def oracle_vjp(plan, f32, c32, w=None):
+    assert_oracle_direction_set(plan)
     weights = np.float32(plan.weights if w is None else w).astype(np.float64)
     return oracle.vjp(plan.dim, plan.n, plan.ntilde, plan.dirs, weights,
                       np.asarray(f32, np.float32).astype(np.float64),
                       np.asarray(c32, np.float32).astype(np.float64))
+
+
+def oracle_grad_w(plan, f32, c32):
+    """grad_w of <c, Q(f; w)> summed over the cells: Q is linear in w, so
+    grad_w[p] = sum_cells <c, Q_p> with Q_p the oracle's unit-weight term of
+    direction p (its direct pair sum)."""
+    assert_oracle_direction_set(plan)
+    f = np.asarray(f32, np.float32).astype(np.float64).reshape(-1, plan.npts)
+    c = np.asarray(c32, np.float32).astype(np.float64).reshape(-1, plan.npts)
+    gw = np.zeros(plan.num_dirs)
+    for k in range(f.shape[0]):
+        terms = oracle.collide_terms(plan.dim, plan.n, plan.ntilde, plan.dirs, f[k])
+        gw += terms @ c[k]
+    return gw
 
 
 def rel_linf(got, ref, scale=None):

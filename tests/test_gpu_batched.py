@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_1201_3986_amd import workloads
-from parity_util import loss_total, oracle_q, rel_linf
+from parity_util import loss_total, oracle_q, per_cell_rel_linf, rel_linf
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -35,6 +35,13 @@ def assert_same_cell(plan, got, single):
         assert np.array_equal(got, single)
     else:
         assert rel_linf(got, single) <= 1e-6
+
+
+def c4_sample(n2, n3, k2=256, k3=64):
+    """Seeded sample of the batched workload's cells checked against the oracle:
+    256 of the 2D cells and 64 of the 3D cells (sorted indices)."""
+    rng = np.random.default_rng(4104)
+    return np.sort(rng.choice(n2, size=k2, replace=False)), np.sort(rng.choice(n3, size=k3, replace=False))
 
 
 def _layout(cells):
@@ -174,15 +181,16 @@ def test_config4_graph_step(gpu_lib):
         qi = qn[o:o + n].astype(np.float64)
         worst_mass = max(worst_mass, abs(qi.sum()) / loss_total(plans[i], flat[o:o + n]))
     print("config4: worst per-cell mass residual (relative to the loss) %.3e" % worst_mass)
-    errs = []
-    for i in list(range(0, len(f2), 512)) + [len(f2), len(f2) + 511]:
-        o, plan = offs[i], plans[i]
-        errs.append(rel_linf(qn[o:o + plan.npts], oracle_q(plan, flat[o:o + plan.npts])))
-    print("config4: sampled cell rel errors (plain FP32): %s" % " ".join("%.2e" % e for e in errs))
+    s2, s3 = c4_sample(len(f2), len(f3))
+    e2 = per_cell_rel_linf(qn[:len(f2) * 1024].reshape(len(f2), -1)[s2], oracle_q(p2, f2[s2]), 1024)
+    e3 = per_cell_rel_linf(qn[len(f2) * 1024:].reshape(len(f3), -1)[s3], oracle_q(p3, f3[s3]), 13824)
+    print("config4 plain FP32: %d 2D cells max rel err %.2e (%d above 1e-5), %d 3D cells max %.2e (%d above)"
+          % (len(s2), e2.max(), int(np.sum(e2 > TOL)), len(s3), e3.max(), int(np.sum(e3 > TOL))))
     assert worst_mass <= 1e-6
-    # plain FP32 cannot reach 1e-5 of max|Q| on these near-equilibrium cells
-    # (gain and loss are 50-100x larger than Q); the near-equilibrium mode does.
-    assert max(errs) <= 1e-4
+    # plain FP32 does not reach 1e-5 of max|Q| on these near-equilibrium cells
+    # (gain and loss are 50-100x larger than Q); the near-equilibrium mode does
+    # (next test).  Here the plain mode is held to its documented bound.
+    assert max(e2.max(), e3.max()) <= 1e-4
 
 
 def test_config4_graph_step_near_equilibrium(gpu_lib):
@@ -228,19 +236,21 @@ def test_config4_graph_step_near_equilibrium(gpu_lib):
     torch.cuda.synchronize()
     assert np.array_equal(qn[:len(f2) * 1024], q2.cpu().numpy().reshape(-1))
     assert np.array_equal(qn[len(f2) * 1024:], q3.cpu().numpy().reshape(-1))
+    s2, s3 = c4_sample(len(f2), len(f3))
     errs, errs_def = [], []
-    for i in list(range(0, len(f2), 512)) + [len(f2), len(f2) + 511]:
-        o, plan = offs[i], plans[i]
-        cell = flat[o:o + plan.npts]
+    for plan, fc, qc, sel in ((p2, f2, qn[:len(f2) * 1024], s2), (p3, f3, qn[len(f2) * 1024:], s3)):
+        cells = fc[sel].astype(np.float64)
+        got = qc.reshape(len(fc), -1)[sel]
+        full = oracle_q(plan, fc[sel]).reshape(len(sel), -1)
         w = np.float32(plan.weights).astype(np.float64)
-        full = oracle.collide(plan.dim, plan.n, plan.ntilde, plan.dirs, w, cell.astype(np.float64))
-        defn = oracle.collide_near_equilibrium(plan.dim, plan.n, plan.ntilde, plan.dirs, w, cell.astype(np.float64))
-        errs.append(rel_linf(qn[o:o + plan.npts], full))
-        errs_def.append(rel_linf(qn[o:o + plan.npts], defn))
-    print("config4 near-eq: sampled rel errors vs Q(f,f): %s" % " ".join("%.2e" % e for e in errs))
-    print("config4 near-eq: sampled rel errors vs definition: %s" % " ".join("%.2e" % e for e in errs_def))
-    assert max(errs) <= TOL
-    assert max(errs_def) <= TOL
+        defn = oracle.collide_near_equilibrium(plan.dim, plan.n, plan.ntilde, plan.dirs, w,
+                                               cells.reshape((len(sel),) + (plan.n,) * plan.dim))
+        errs.append(per_cell_rel_linf(got, full, plan.npts))
+        errs_def.append(per_cell_rel_linf(got, defn.reshape(len(sel), -1), plan.npts))
+    print("config4 near-eq: %d 2D + %d 3D cells, max rel err vs Q(f,f) %.2e / %.2e, vs definition %.2e / %.2e"
+          % (len(s2), len(s3), errs[0].max(), errs[1].max(), errs_def[0].max(), errs_def[1].max()))
+    assert max(e.max() for e in errs) <= TOL
+    assert max(e.max() for e in errs_def) <= TOL
     # mixed batch: plain and near-equilibrium plans of every family together
     pf2 = gpu_lib.Plan(2, 32, 8.0, num_dirs=16)
     p64 = gpu_lib.Plan(2, 64, 8.0, num_dirs=8, mode=near)
@@ -296,3 +306,41 @@ def test_rk2_graph_step(gpu_lib):
         gpu_lib.StepGraph(b, x, dt, s, scheme=5)
     with pytest.raises(ValueError):
         gpu_lib.StepGraph(b, x, dt, s, scheme="rk4")
+
+
+def test_one_shot_eval_batched(gpu_lib):
+    """qdvm_eval_batched (build, evaluate, synchronise, destroy in one call)
+    gives the persistent batch's result bit for bit, for Q and for the Euler
+    update, and its cells agree with the oracle."""
+    import torch
+    p32 = gpu_lib.Plan(2, 32, 8.0, num_dirs=16)
+    p64 = gpu_lib.Plan(2, 64, 8.0, num_dirs=8)
+    p24 = gpu_lib.Plan(3, 24, 8.0, num_dirs=16)
+    cells = [(p32, workloads.random_positive(1500 + i, 2, 32)[0]) for i in range(13)]
+    cells += [(p64, workloads.random_positive(1600 + i, 2, 64)[0]) for i in range(3)]
+    cells += [(p24, workloads.random_positive(1700 + i, 3, 24)[0]) for i in range(2)]
+    order = np.random.default_rng(18).permutation(len(cells))
+    cells = [cells[k] for k in order]
+    flat, offs = _layout(cells)
+    plans = [c[0] for c in cells]
+    b = gpu_lib.BatchPlan(plans, offs)
+    fd = _dev(flat)
+    want = b.eval(fd, out=torch.full_like(fd, -7.0))
+    torch.cuda.synchronize()
+    out = torch.full_like(fd, -7.0)
+    gpu_lib.eval_batched(plans, offs, fd, out)
+    got = out.cpu().numpy()
+    assert np.array_equal(got, want.cpu().numpy())
+    for k in (0, len(cells) // 2, len(cells) - 1):
+        plan, a = cells[k]
+        o = offs[k]
+        assert rel_linf(got[o:o + plan.npts], oracle_q(plan, a)) <= TOL
+    # Euler update in place through the one-shot call
+    x = _dev(flat)
+    gpu_lib.eval_batched(plans, offs, x, x, dt=0.01)
+    ref = _dev(flat)
+    b.eval(ref, out=ref, dt=0.01)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), ref.cpu().numpy())
+    # empty batch: nothing to do
+    gpu_lib.eval_batched([], [], fd, out)
