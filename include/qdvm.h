@@ -151,6 +151,25 @@ qdvm_status qdvm_eval(qdvm_plan_t plan, int32_t batch, const float* f, float* q,
                       float dt, hipStream_t stream);
 
 /*
+ * qdvm_eval for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments and results, but the scratch of the launch is a static
+ * device array of this library (qdvm_noalloc_scratch_bytes(): 32 MiB per GPU,
+ * held until the process ends) instead of the plan's workspace.  The call
+ * allocates, frees and synchronises nothing; if the natural launch's resident
+ * cells do not fit in the array it runs fewer, persistent workgroups (never
+ * a direction-split launch), so results equal qdvm_eval's up to summation
+ * order (bit for bit in 2D).  EINVAL if one resident cell of the plan needs
+ * more scratch than the array holds.  Every call on one GPU uses that GPU's
+ * one array: calls that overlap in time on one GPU (concurrent streams or
+ * threads) race and must be serialised by the caller.  The plan itself is
+ * created beforehand (qdvm_plan allocates).
+ */
+qdvm_status qdvm_eval_noalloc(qdvm_plan_t plan, int32_t batch, const float* f, float* q, const float* w,
+                              float dt, hipStream_t stream);
+size_t qdvm_noalloc_scratch_bytes(void);
+
+/*
  * Vector-Jacobian product of Q with respect to f and the weights, for `batch`
  * cells sharing the plan, with cotangent `cot`:
  *   grad_f  device, batch * n^d floats, overwritten: d<cot, Q>/df per cell.

@@ -257,6 +257,47 @@ qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, co
 }
 
 
+// Evaluation whose scratch lives in the given buffer (ws, ws_bytes) instead of
+// the plan's workspace: one workgroup per cell (no direction split) and, if the
+// resident slots of the natural launch do not fit, fewer workgroups, each
+// persistent over more cells.
+qdvm_status eval_in(qdvm_plan_s* p, int batch, const float* f, float* q, const float* w, float dt, hipStream_t st,
+                    int variant, void* ws, size_t ws_bytes)
+{
+    qdvm::HostPlan& hp = p->hp;
+    const qdvm::DevPlan pl = hp.dev();
+    qdvm::LaunchLimits lim;
+    lim.allow_split = false;
+    qdvm::LaunchInfo li = qdvm::eval_launch_info(pl, batch, variant, lim);
+    if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
+    WsLayout L = call_layout(hp, li, batch, false);
+    while (L.total > ws_bytes && li.grid > 1) {
+        int g = (int)((double)li.grid * (double)ws_bytes / (double)L.total);
+        lim.max_grid = std::max(1, std::min(g, li.grid - 1));
+        li = qdvm::eval_launch_info(pl, batch, variant, lim);
+        if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
+        L = call_layout(hp, li, batch, false);
+    }
+    if (L.total > ws_bytes) {
+        char m[160];
+        std::snprintf(m, sizeof m, "one resident cell of this plan needs %zu bytes of scratch, more than the %zu available",
+                      L.total, ws_bytes);
+        return fail(QDVM_EINVAL, m);
+    }
+    qdvm::DevScratch sc = scratch_of(ws, hp, L, false, li.jsplit);
+    hipError_t e = hipSuccess;
+    if (w) {
+        e = qdvm::launch_prep(pl, w, sc, st);
+        if (e != hipSuccess) return from_hip(e, "launching the multiplier preparation");
+    } else {
+        sc.lam = hp.d_lam0;
+        sc.jobw = hp.d_jobw0;
+    }
+    e = qdvm::launch_eval(pl, batch, f, q, dt, sc, li, variant, st);
+    if (e != hipSuccess) return from_hip(e, "launching the collision kernel");
+    return QDVM_OK;
+}
+
 int batch_class(int dim, int n)
 {
     if (dim == 2) {
@@ -455,6 +496,30 @@ qdvm_status qdvm_eval(qdvm_plan_t p, int32_t batch, const float* f, float* q, co
     if (s != QDVM_OK) return s;
     return do_eval(p, batch, f, q, w, dt, stream, effective_variant(p, 0));
 }
+
+}  // extern "C"
+
+namespace qdvm {
+
+qdvm_status eval_with_scratch(qdvm_plan_t p, int32_t batch, const float* f, float* q, const float* w, float dt,
+                              hipStream_t stream, void* ws, size_t ws_bytes)
+{
+    if (!p) return fail(QDVM_EINVAL, "null plan");
+    if (batch < 0) return fail(QDVM_EINVAL, "negative batch");
+    if (batch == 0) return QDVM_OK;
+    if (!f || !q) return fail(QDVM_EINVAL, "null f or q");
+    if (!std::isfinite(dt)) return fail(QDVM_EINVAL, "dt must be finite");
+    std::lock_guard<std::mutex> lock(p->mu);
+    qdvm_status s = check_device(p);
+    if (s != QDVM_OK) return s;
+    return eval_in(p, batch, f, q, w, dt, stream, effective_variant(p, 0), ws, ws_bytes);
+}
+
+qdvm_status record_error(qdvm_status st, const char* msg) { return fail(st, msg); }
+
+}  // namespace qdvm
+
+extern "C" {
 
 qdvm_status qdvm_vjp(qdvm_plan_t p, int32_t batch, const float* f, const float* cot, const float* w,
                      float* grad_f, float* grad_w, hipStream_t stream)

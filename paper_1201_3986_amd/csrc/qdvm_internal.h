@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/qdvm.h"
+
 #include <string>
 #include <vector>
 
@@ -189,6 +191,13 @@ hipError_t launch_batched(int family, const BatchDev& b, const LaunchInfo& li, c
 // f[c] <- (f[c] + f1[c]) / 2 over the cells (offset, count) of a batch
 hipError_t launch_average_cells(const int64_t* off, const int32_t* cnt, int ncells, float* f, const float* f1,
                                 hipStream_t st);
+
+// Evaluation of qdvm_eval with its scratch in the caller's device buffer
+// (ws, ws_bytes) instead of the plan's workspace (capi.cpp).
+qdvm_status eval_with_scratch(qdvm_plan_s* p, int32_t batch, const float* f, float* q, const float* w, float dt,
+                              hipStream_t stream, void* ws, size_t ws_bytes);
+// Sets the calling thread's last-error text and returns st.
+qdvm_status record_error(qdvm_status st, const char* msg);
 
 int num_variants(int dim, int n);
 int default_variant(int dim, int n);

@@ -63,6 +63,7 @@ def load():
             "qdvm_describe": [ctypes.POINTER(Desc), i32p, i32p, dp, i32p, i32],
             "qdvm_eval": [vp, i32, vp, vp, vp, ctypes.c_float, vp],
             "qdvm_vjp": [vp, i32, vp, vp, vp, vp, vp, vp],
+            "qdvm_eval_noalloc": [vp, i32, vp, vp, vp, ctypes.c_float, vp],
             "qdvm_set_variant": [vp, i32, i32],
             "qdvm_get_variant": [vp, i32, i32p],
             "qdvm_autotune": [vp, i32, vp],
@@ -88,6 +89,7 @@ def load():
         lib.qdvm_status_string.restype = ctypes.c_char_p
         lib.qdvm_last_error.restype = ctypes.c_char_p
         lib.qdvm_abi_version.restype = ctypes.c_int32
+        lib.qdvm_noalloc_scratch_bytes.restype = ctypes.c_size_t
         if lib.qdvm_abi_version() != ABI_VERSION:
             raise ImportError("libqdvm.so has ABI %d, the binding expects %d; rebuild it"
                               % (lib.qdvm_abi_version(), ABI_VERSION))
@@ -222,6 +224,17 @@ class Plan:
             raise ValueError("out and f differ in size")
         w = self._weights(w)
         _check(load().qdvm_eval(self._h, batch, _ptr(f), _ptr(out), _ptr(w), float(dt), _stream_ptr(stream)))
+        return out
+
+    def eval_noalloc(self, f, out, w=None, dt=0.0, stream=None):
+        """As eval, through qdvm_eval_noalloc: the launch's scratch is the
+        library's static device array (nothing is allocated); out is required."""
+        batch = self._cells(f, "f")
+        if self._cells(out, "out") != batch:
+            raise ValueError("out and f differ in size")
+        w = self._weights(w)
+        _check(load().qdvm_eval_noalloc(self._h, batch, _ptr(f), _ptr(out), _ptr(w), float(dt),
+                                        _stream_ptr(stream)))
         return out
 
     def vjp(self, f, cot, w=None, want_grad_w=True, stream=None):
