@@ -11,6 +11,7 @@ from .oracle import (  # noqa: F401
     default_weights,
     default_ntilde,
     collide,
+    collide_bilinear,
     collide_terms,
     vjp,
     num_threads,

@@ -56,6 +56,7 @@ def _load():
         lib.oracle_default_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, i32p, dp]
         lib.oracle_collide.argtypes = [ctypes.c_int] * 4 + [i32p, dp, ctypes.c_int, dp, dp]
         lib.oracle_collide_terms.argtypes = [ctypes.c_int] * 4 + [i32p, dp, dp]
+        lib.oracle_collide_bilinear.argtypes = [ctypes.c_int] * 4 + [i32p, dp, ctypes.c_int, dp, dp, dp]
         lib.oracle_vjp.argtypes = [ctypes.c_int] * 4 + [i32p, dp, ctypes.c_int, dp, dp, dp, dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -127,6 +128,23 @@ def collide(d, n, ntilde, dirs, w, f) -> np.ndarray:
     lib.oracle_collide(d, n, ntilde, len(dirs), dptr, wptr, batch,
                        f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return q
+
+
+def collide_bilinear(d, n, ntilde, dirs, w, g, f) -> np.ndarray:
+    """Q(g, f) by direct summation (gain g(i+k) f(i+l), loss g(i) f(i+k+l));
+    g and f of the same shape, one or more cells."""
+    lib = _load()
+    g, batch = _cells(g, d, n)
+    f, batch_f = _cells(f, d, n)
+    if batch_f != batch:
+        raise ValueError("g and f differ in size")
+    dirs, dptr = _i32(dirs)
+    w, wptr = _f64(w)
+    q = np.zeros_like(f)
+    P = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_collide_bilinear(d, n, ntilde, len(dirs), dptr, wptr, batch, g.ctypes.data_as(P),
+                                f.ctypes.data_as(P), q.ctypes.data_as(P))
     return q
 
 

@@ -276,6 +276,52 @@ void oracle_collide(int d, int n, int ntilde, int P, const int32_t *dirs, const 
 }
 
 /*
+ * The bilinear operator of the consistency statement of Sec. 2.3 (Theorem
+ * theo:HePa is stated for D(g, f)): eq. (2.9) with the two distribution
+ * functions in the places the paper's Q(g, f) gives them -- g at the point
+ * i + k of the gain and at i itself in the loss, f at i + l and i + k + l:
+ *
+ *   Q(g, f)_i = sum_p w_p sum_{k in K_p, l in L_p} [ g(i+k) f(i+l) - g(i) f(i+k+l) ]
+ *
+ * Q(f, f) is the diagonal.  Same sets and weights as oracle_collide.
+ */
+void oracle_collide_bilinear(int d, int n, int ntilde, int P, const int32_t *dirs, const double *w,
+                             int batch, const double *g, const double *f, double *q)
+{
+    long npts = or_npts(d, n);
+    or_sets *s = (or_sets *)malloc(sizeof(or_sets) * (size_t)(P > 0 ? P : 1));
+    for (int p = 0; p < P; ++p) or_build_sets(d, ntilde, dirs + (size_t)p * d, &s[p]);
+    for (int cell = 0; cell < batch; ++cell) {
+        const double *gc = g + (size_t)cell * npts;
+        const double *fc = f + (size_t)cell * npts;
+        double *qc = q + (size_t)cell * npts;
+#pragma omp parallel for schedule(static)
+        for (long flat = 0; flat < npts; ++flat) {
+            int i[OR_MAXD];
+            or_coords(d, n, flat, i);
+            double total = 0.0;
+            for (int p = 0; p < P; ++p) {
+                double acc = 0.0;
+                for (int a = 0; a < s[p].nk; ++a) {
+                    const int *k = s[p].k + (size_t)a * d;
+                    long ik = or_wrap(d, n, i, k, NULL);
+                    for (int b = 0; b < s[p].nl; ++b) {
+                        const int *l = s[p].l + (size_t)b * d;
+                        long il = or_wrap(d, n, i, l, NULL);
+                        long ikl = or_wrap(d, n, i, k, l);
+                        acc += gc[ik] * fc[il] - gc[flat] * fc[ikl];
+                    }
+                }
+                total += w[p] * acc;
+            }
+            qc[flat] = total;
+        }
+    }
+    for (int p = 0; p < P; ++p) or_free_sets(&s[p]);
+    free(s);
+}
+
+/*
  * Vector-Jacobian product.  With a cotangent c, the scalar <c, Q(f; w)> has
  *
  *   d/df_j : sum_p w_p sum_{k in K_p, l in L_p} ( c[j-k] f[j-k+l] + c[j-l] f[j-l+k]
