@@ -138,6 +138,19 @@ def cell_errors(plan, f_np, q_np, idx, near_equilibrium_definition=False):
     return np.max(np.abs(got - ref), axis=1) / np.max(np.abs(ref), axis=1)
 
 
+def bilinear_errors(plan, g_np, f_np, q_np, idx):
+    """Largest relative L-infinity error of the listed cells of Q(g, f) against
+    the oracle's pair sum."""
+    import oracle
+    w = np.float32(plan.weights).astype(np.float64)
+    worst = 0.0
+    for c in idx:
+        ref = oracle.collide_bilinear(plan.dim, plan.n, plan.ntilde, plan.dirs, w,
+                                      np.asarray(g_np[c], np.float64), np.asarray(f_np[c], np.float64)).reshape(-1)
+        worst = max(worst, float(np.max(np.abs(np.asarray(q_np[c], np.float64).reshape(-1) - ref)) / np.max(np.abs(ref))))
+    return worst
+
+
 def sampled_error(plan, f_np, q_np, idx):
     return float(np.max(cell_errors(plan, f_np, q_np, idx)))
 
@@ -398,6 +411,16 @@ def main():
         log("near-equilibrium 2D n=64 P=16: %.3f ms, rel err vs definition %.2e, vs Q(f,f) %.2e"
             % (t, e_def.max(), e_ff.max()))
         pn.close()
+        # bilinear Q(g, f) on the headline cells, g = the cells shifted by one
+        gsh = torch.roll(f, 1, dims=0).contiguous()
+        tb = time_calls(lambda: plan.eval_bilinear(gsh, f, out=q), max(5, args.steps // 4), 2)
+        eb = bilinear_errors(plan, np.roll(f_np, 1, axis=0), f_np, q.cpu().numpy(), range(0, n_check, 32))
+        results["bilinear_2d_n64_P16"] = {
+            "ms": tb, "cells_per_s": B / (tb * 1e-3), "eval_ms_same_batch": ms, "bilinear_over_eval": tb / ms,
+            "rel_err": eb, "rel_err_cells": len(range(0, n_check, 32)),
+            "note": "Q(g, f) with g the cells shifted by one: 2 forward + 1 loss + P inverse transforms per cell"}
+        log("bilinear Q(g,f) 2D n=64 P=16: %.3f ms (eval %.3f ms), rel err %.2e" % (tb, ms, eb))
+        del gsh
         # 2D adjoint on the headline cells (same f, a N(0,1) cotangent)
         cot = torch.from_numpy(np.random.default_rng(106).standard_normal(f.shape).astype(np.float32)).cuda()
         tv = time_calls(lambda: plan.vjp(f, cot), max(5, args.steps // 5), 2)
@@ -424,6 +447,14 @@ def main():
                                          "rel_err_cells": 4,
                                          "tflops": algorithmic_flops(3, 32, pl.num_jobs) * C3 / (t * 1e-3) / 1e12}
             log("3D n=32 P=%d: %.3f ms for %d cells, rel err %.2e" % (P, t, C3, e))
+            if P == 16:
+                g3 = torch.roll(f3, 1, dims=0).contiguous()
+                tb = time_calls(lambda: pl.eval_bilinear(g3, f3, out=q3), max(5, args.steps // 5), 2)
+                eb = bilinear_errors(pl, np.roll(f3_np, 1, axis=0), f3_np, q3.cpu().numpy(), [1, 40])
+                results["bilinear_3d_n32_P16"] = {"ms": tb, "cells_per_s": C3 / (tb * 1e-3), "eval_ms_same_batch": t,
+                                                  "bilinear_over_eval": tb / t, "rel_err": eb, "rel_err_cells": 2}
+                log("bilinear Q(g,f) 3D n=32 P=16: %.3f ms (eval %.3f ms), rel err %.2e" % (tb, t, eb))
+                del g3
             if P == 16:
                 # adjoint on the differentiation workload shape (64 cells, P = 16)
                 c5 = workloads.c5()

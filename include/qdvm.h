@@ -151,6 +151,29 @@ qdvm_status qdvm_eval(qdvm_plan_t plan, int32_t batch, const float* f, float* q,
                       float dt, hipStream_t stream);
 
 /*
+ * The bilinear operator Q(g, f) for `batch` cells sharing the plan (the
+ * consistency statement of Sec. 2.3 is written for D(g, f); Q(f, f) is its
+ * diagonal):
+ *   Q(g, f)_i = sum_p w_p sum_{0<|m|<=M_p} sum_{l.e_p=0, |l|_inf<=Nt}
+ *                 [ g(i + m e_p) f(i + l) - g(i) f(i + m e_p + l) ],
+ * i.e. the gain takes g along the line and f over the plane, the loss is
+ * g(i) times the collision frequency of f.
+ *   g, f  device, batch * n^d floats each, cells back to back.
+ *   q     device, batch * n^d floats: q = Q(g, f) when dt == 0, else the
+ *         forward Euler update of the first argument, q = g + dt Q(g, f)
+ *         (the evolution of g in the field of f).  q may equal g or f;
+ *         partial overlap is not allowed.
+ *   w     optional device array of P FP32 weights, as in qdvm_eval.
+ * The plan's evaluation mode is ignored (always the plain FP32 form), and
+ * the kernel variant is the evaluation's (op 0).  Each direction costs one
+ * inverse transform (2D perpendicular pairs do not share one here: Q(g, f) is
+ * not symmetric under exchanging the two lines), plus two forward transforms
+ * and one loss transform per cell.  Never allocates or synchronises.
+ */
+qdvm_status qdvm_eval_bilinear(qdvm_plan_t plan, int32_t batch, const float* g, const float* f, float* q,
+                               const float* w, float dt, hipStream_t stream);
+
+/*
  * qdvm_eval for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same arguments and results, but the scratch of the launch is a static

@@ -112,6 +112,8 @@ void free_device(qdvm::HostPlan& hp)
     hipFree(hp.d_dir_job);
     hipFree(hp.d_lam0);
     hipFree(hp.d_jobw0);
+    hipFree(hp.d_lamb0);
+    hipFree(hp.d_dirw0);
     hipFree(hp.d_ws);
     hp.d_jobs = nullptr;
     hp.d_dirichlet = nullptr;
@@ -120,6 +122,8 @@ void free_device(qdvm::HostPlan& hp)
     hp.d_dir_job = nullptr;
     hp.d_lam0 = nullptr;
     hp.d_jobw0 = nullptr;
+    hp.d_lamb0 = nullptr;
+    hp.d_dirw0 = nullptr;
     hp.d_ws = nullptr;
     hp.ws_bytes = 0;
 }
@@ -140,20 +144,25 @@ struct WsLayout {
     size_t lam, jobw, spec, spec2, acc, gw, part, total;
 };
 
+// Kinds of launch that draw on the workspace.
+enum WsKind { WS_EVAL = 0, WS_ADJOINT = 1, WS_BILINEAR = 2 };
+
 // slots: resident cell slots of the launch; rows: grad_w partial rows;
 // part_cells: workgroups of a direction-split launch (0 if none).
-WsLayout ws_layout(const qdvm::HostPlan& hp, size_t slots, size_t rows, size_t part_cells, bool adjoint)
+WsLayout ws_layout(const qdvm::HostPlan& hp, size_t slots, size_t rows, size_t part_cells, int kind)
 {
     WsLayout L{};
     const size_t npts = (size_t)hp.npts();
     const size_t njobs = std::max<size_t>(1, hp.jobs.size());
+    const bool adjoint = kind == WS_ADJOINT;
     size_t off = 0;
     L.lam = off; off = align_up(off + sizeof(float) * npts);
-    L.jobw = off; off = align_up(off + sizeof(float) * njobs);
+    // job weights, or the per-direction weights of the bilinear operator
+    L.jobw = off; off = align_up(off + sizeof(float) * std::max<size_t>(njobs, (size_t)hp.P));
     L.spec = off; off = align_up(off + sizeof(float2) * npts * slots);
-    if (adjoint || hp.mode) {
-        // adjoint: one slot set; near-equilibrium evaluation: g and a staging set
-        L.spec2 = off; off = align_up(off + sizeof(float2) * npts * slots * (adjoint ? 1 : 2));
+    if (adjoint || kind == WS_BILINEAR || hp.mode) {
+        // adjoint: R; bilinear: the transform of g; near-equilibrium evaluation: g and a staging set
+        L.spec2 = off; off = align_up(off + sizeof(float2) * npts * slots * (kind == WS_EVAL ? 2 : 1));
     }
     if (adjoint) {
         L.acc = off; off = align_up(off + sizeof(float2) * npts * slots);
@@ -166,11 +175,11 @@ WsLayout ws_layout(const qdvm::HostPlan& hp, size_t slots, size_t rows, size_t p
     return L;
 }
 
-WsLayout call_layout(const qdvm::HostPlan& hp, const qdvm::LaunchInfo& li, int batch, bool adjoint)
+WsLayout call_layout(const qdvm::HostPlan& hp, const qdvm::LaunchInfo& li, int batch, int kind)
 {
     const size_t slots = (size_t)li.slots;
     return ws_layout(hp, slots, std::min<size_t>((size_t)batch, slots), li.jsplit > 1 ? (size_t)li.grid : 0,
-                     adjoint);
+                     kind);
 }
 
 // Workspace that serves every batch size, variant and operation of a plan:
@@ -179,24 +188,26 @@ qdvm_status workspace_bound(const qdvm::HostPlan& hp, size_t& bytes)
 {
     const qdvm::DevPlan pl = hp.dev();
     bytes = 0;
-    for (int op = 0; op < 2; ++op)
+    for (int op = 0; op < 3; ++op)
         for (int v = 0; v < qdvm::num_variants(hp.dim, hp.n); ++v) {
             const int slots = qdvm::max_slots(pl, op, v);
             if (slots <= 0) return fail(QDVM_EDEVICE, "could not size the plan workspace (occupancy query failed)");
-            const WsLayout L = ws_layout(hp, (size_t)slots, (size_t)slots, hp.dim == 3 ? (size_t)slots : 0, op == 1);
+            const WsLayout L = ws_layout(hp, (size_t)slots, (size_t)slots,
+                                         (hp.dim == 3 && op != 2) ? (size_t)slots : 0, op);
             bytes = std::max(bytes, L.total);
         }
     return QDVM_OK;
 }
 
-qdvm::DevScratch scratch_of(void* base, const qdvm::HostPlan& hp, const WsLayout& L, bool adjoint, int jsplit)
+qdvm::DevScratch scratch_of(void* base, const qdvm::HostPlan& hp, const WsLayout& L, int kind, int jsplit)
 {
+    const bool adjoint = kind == WS_ADJOINT;
     char* b = (char*)base;
     qdvm::DevScratch s{};
     s.lam = (float*)(b + L.lam);
     s.jobw = (float*)(b + L.jobw);
     s.spec = (float2*)(b + L.spec);
-    if (adjoint || hp.mode) s.spec2 = (float2*)(b + L.spec2);
+    if (adjoint || kind == WS_BILINEAR || hp.mode) s.spec2 = (float2*)(b + L.spec2);
     if (adjoint) {
         s.acc = (float2*)(b + L.acc);
         s.gw_part = (double*)(b + L.gw);
@@ -217,9 +228,9 @@ qdvm_status do_eval(qdvm_plan_s* p, int batch, const float* f, float* q, const f
     const qdvm::DevPlan pl = hp.dev();
     qdvm::LaunchInfo li = qdvm::eval_launch_info(pl, batch, variant);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
-    const WsLayout L = call_layout(hp, li, batch, false);
+    const WsLayout L = call_layout(hp, li, batch, WS_EVAL);
     if (L.total > hp.ws_bytes) return fail(QDVM_EDEVICE, "internal: launch needs more than the plan workspace");
-    qdvm::DevScratch sc = scratch_of(hp.d_ws, hp, L, false, li.jsplit);
+    qdvm::DevScratch sc = scratch_of(hp.d_ws, hp, L, WS_EVAL, li.jsplit);
     hipError_t e = hipSuccess;
     if (w) {
         e = qdvm::launch_prep(pl, w, sc, st);
@@ -240,9 +251,9 @@ qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, co
     const qdvm::DevPlan pl = hp.dev();
     qdvm::LaunchInfo li = qdvm::vjp_launch_info(pl, batch, variant);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the adjoint kernel");
-    const WsLayout L = call_layout(hp, li, batch, true);
+    const WsLayout L = call_layout(hp, li, batch, WS_ADJOINT);
     if (L.total > hp.ws_bytes) return fail(QDVM_EDEVICE, "internal: launch needs more than the plan workspace");
-    qdvm::DevScratch sc = scratch_of(hp.d_ws, hp, L, true, li.jsplit);
+    qdvm::DevScratch sc = scratch_of(hp.d_ws, hp, L, WS_ADJOINT, li.jsplit);
     hipError_t e = hipSuccess;
     if (w) {
         e = qdvm::launch_prep(pl, w, sc, st);
@@ -257,6 +268,29 @@ qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, co
 }
 
 
+qdvm_status do_eval_bilinear(qdvm_plan_s* p, int batch, const float* g, const float* f, float* q, const float* w,
+                             float dt, hipStream_t st, int variant)
+{
+    qdvm::HostPlan& hp = p->hp;
+    const qdvm::DevPlan pl = hp.dev();
+    qdvm::LaunchInfo li = qdvm::bilinear_launch_info(pl, batch, variant);
+    if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the bilinear kernel");
+    const WsLayout L = call_layout(hp, li, batch, WS_BILINEAR);
+    if (L.total > hp.ws_bytes) return fail(QDVM_EDEVICE, "internal: launch needs more than the plan workspace");
+    qdvm::DevScratch sc = scratch_of(hp.d_ws, hp, L, WS_BILINEAR, li.jsplit);
+    hipError_t e = hipSuccess;
+    if (w) {
+        e = qdvm::launch_prep_bilinear(pl, w, sc, st);
+        if (e != hipSuccess) return from_hip(e, "launching the multiplier preparation");
+    } else {
+        sc.lam = hp.d_lamb0;
+        sc.jobw = hp.d_dirw0;
+    }
+    e = qdvm::launch_eval_bilinear(pl, batch, g, f, q, dt, sc, li, variant, st);
+    if (e != hipSuccess) return from_hip(e, "launching the bilinear kernel");
+    return QDVM_OK;
+}
+
 // Evaluation whose scratch lives in the given buffer (ws, ws_bytes) instead of
 // the plan's workspace: one workgroup per cell (no direction split) and, if the
 // resident slots of the natural launch do not fit, fewer workgroups, each
@@ -270,13 +304,13 @@ qdvm_status eval_in(qdvm_plan_s* p, int batch, const float* f, float* q, const f
     lim.allow_split = false;
     qdvm::LaunchInfo li = qdvm::eval_launch_info(pl, batch, variant, lim);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
-    WsLayout L = call_layout(hp, li, batch, false);
+    WsLayout L = call_layout(hp, li, batch, WS_EVAL);
     while (L.total > ws_bytes && li.grid > 1) {
         int g = (int)((double)li.grid * (double)ws_bytes / (double)L.total);
         lim.max_grid = std::max(1, std::min(g, li.grid - 1));
         li = qdvm::eval_launch_info(pl, batch, variant, lim);
         if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
-        L = call_layout(hp, li, batch, false);
+        L = call_layout(hp, li, batch, WS_EVAL);
     }
     if (L.total > ws_bytes) {
         char m[160];
@@ -284,7 +318,7 @@ qdvm_status eval_in(qdvm_plan_s* p, int batch, const float* f, float* q, const f
                       L.total, ws_bytes);
         return fail(QDVM_EINVAL, m);
     }
-    qdvm::DevScratch sc = scratch_of(ws, hp, L, false, li.jsplit);
+    qdvm::DevScratch sc = scratch_of(ws, hp, L, WS_EVAL, li.jsplit);
     hipError_t e = hipSuccess;
     if (w) {
         e = qdvm::launch_prep(pl, w, sc, st);
@@ -391,11 +425,16 @@ qdvm_status qdvm_plan(const qdvm_desc* desc, qdvm_plan_t* out)
     // Lambda and the job weights for the plan's own weights, computed once
     if (e == hipSuccess) e = hipMalloc(&hp.d_lam0, sizeof(float) * hp.npts());
     if (e == hipSuccess) e = hipMalloc(&hp.d_jobw0, sizeof(float) * std::max<size_t>(1, hp.jobs.size()));
+    if (e == hipSuccess) e = hipMalloc(&hp.d_lamb0, sizeof(float) * hp.npts());
+    if (e == hipSuccess) e = hipMalloc(&hp.d_dirw0, sizeof(float) * std::max<size_t>(1, (size_t)hp.P));
     if (e == hipSuccess) {
         qdvm::DevScratch sc{};
         sc.lam = hp.d_lam0;
         sc.jobw = hp.d_jobw0;
         e = qdvm::launch_prep(hp.dev(), hp.d_w, sc, nullptr);
+        sc.lam = hp.d_lamb0;
+        sc.jobw = hp.d_dirw0;
+        if (e == hipSuccess) e = qdvm::launch_prep_bilinear(hp.dev(), hp.d_w, sc, nullptr);
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     }
     if (e != hipSuccess) {
@@ -520,6 +559,20 @@ qdvm_status record_error(qdvm_status st, const char* msg) { return fail(st, msg)
 }  // namespace qdvm
 
 extern "C" {
+
+qdvm_status qdvm_eval_bilinear(qdvm_plan_t p, int32_t batch, const float* g, const float* f, float* q,
+                               const float* w, float dt, hipStream_t stream)
+{
+    if (!p) return fail(QDVM_EINVAL, "null plan");
+    if (batch < 0) return fail(QDVM_EINVAL, "negative batch");
+    if (batch == 0) return QDVM_OK;
+    if (!g || !f || !q) return fail(QDVM_EINVAL, "null g, f or q");
+    if (!std::isfinite(dt)) return fail(QDVM_EINVAL, "dt must be finite");
+    std::lock_guard<std::mutex> lock(p->mu);
+    qdvm_status s = check_device(p);
+    if (s != QDVM_OK) return s;
+    return do_eval_bilinear(p, batch, g, f, q, w, dt, stream, effective_variant(p, 0));
+}
 
 qdvm_status qdvm_vjp(qdvm_plan_t p, int32_t batch, const float* f, const float* cot, const float* w,
                      float* grad_f, float* grad_w, hipStream_t stream)

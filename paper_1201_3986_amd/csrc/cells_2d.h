@@ -184,6 +184,111 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
 }
 
 
+// Bilinear operator Q(g, f) of one 2D cell: gain g(i+k) f(i+l), loss
+// g(i) f(i+k+l) (Sec. 2.3 states consistency for D(g, f); its Fourier form
+// of Sec. 3.1 carries g~_K f~_L).  The transforms of g and f are kept as half
+// spectra in two slots (rgh, it.fh); each direction is one inverse transform
+// of alpha_p ghat + i alpha'_p fhat, real part the line sum of g along e_p,
+// imaginary part the plane sum of f.  A job of the plan that pairs e with
+// e_perp runs two transforms here: the shared transform of Q(f, f) rests on
+// its symmetry under exchanging the two lines (Remark 3.5), which Q(g, f)
+// lacks.  rlam: Lambda = sum_p w_p alpha_p alpha'_p over the unpaired
+// directions (/ n^2); dirw: per-direction weights / n^4.  it.f holds f, rg
+// holds g; the Euler form updates g: q = g + dt Q(g, f).
+template <int N, int RV>
+__device__ __forceinline__ void cell2d_eval_bilinear(const DevPlan& pl, const Item2D& it, rsrc_t rg, rsrc_t rgh,
+                                                     rsrc_t rlam, const float* __restrict__ dirw, float dt,
+                                                     bool valid, float* xb, const float* dtab, int j)
+{
+    constexpr int RS = N * 4;
+    float2 z[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) z[i] = make_float2(bload(rg, it.vcell, i * RS), 0.f);
+    fwd2d<N, RV>(z, xb, j);
+    const HalfSpec<N, N * 8> gh = half2d<N>(rgh, it.vspec, j);
+    gh.put(z);
+#pragma unroll
+    for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
+    fwd2d<N, RV>(z, xb, j);
+    const HalfSpec<N, N * 8> fh = half2d<N>(it.fh, it.vspec, j);
+    fh.put(z);
+
+    // loss: l = Re IFFT(Lambda fhat); acc = -g l
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float l = bload(rlam, j * 4, k * RS);
+        z[k].x *= l;
+        z[k].y *= l;
+    }
+    inv2d<N, RV>(z, xb, j);
+    float acc[N];
+    {
+        const int vc = reread(it.vcell);
+        constexpr int C = N < 16 ? N : 16;
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += C) {
+            float gv[C];
+            load_run<C>(gv, rg, vc, i0, RS);
+#pragma unroll
+            for (int i = 0; i < C; ++i) acc[i0 + i] = -gv[i] * z[i0 + i].x;
+        }
+    }
+
+    // directions: u + i v = IFFT(alpha ghat + i alpha' fhat), acc += w u v
+    const float* atab = dtab_alpha(dtab, pl);
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = gload(pl.jobs, jb);
+        const int nt = J.pp >= 0 ? 2 : 1;
+        for (int t = 0; t < nt; ++t) {
+            // t = 0: line e (alpha = D_M(e.K) - 1), plane e_perp (alpha' = D_M(e_perp.K));
+            // t = 1: the perpendicular direction, the two roles exchanged.  Along the lane's
+            // row K0 = j, e.K starts at e_0 j and steps by e_1; e_perp.K at -e_1 j, step e_0.
+            const float cw = gload(dirw, t ? J.pp : J.p);
+            const int se = modc<N>(J.e[0] * j), de = modc<N>(J.e[1]);
+            const int sp = modc<N>(-J.e[1] * j), dp = modc<N>(J.e[0]);
+            RowWalk<N> a(atab + J.M * N, t ? sp : se, t ? dp : de);
+            RowWalk<N> b(dtab + J.M * N, t ? se : sp, t ? de : dp);
+            // chunks of 8 elements (2 at n = 64, where the pencil, the accumulator
+            // and both spectra's chunk fill the register budget)
+            constexpr int C = N < 8 ? N : (N == 64 ? 2 : 8);
+#pragma unroll
+            for (int k0 = 0; k0 < N; k0 += C) {
+                float2 G[C], F[C];
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    G[i] = gh.get(k0 + i);
+                    F[i] = fh.get(k0 + i);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const float al = a.get(), ap = b.get();
+                    z[k0 + i] = make_float2(__builtin_fmaf(al, G[i].x, -ap * F[i].y),
+                                            __builtin_fmaf(al, G[i].y, ap * F[i].x));
+                    a.next();
+                    b.next();
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            inv2d<N, RV>(z, xb, j);
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
+        }
+    }
+
+    if (!valid) return;
+    if (dt == 0.f) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) bstore(acc[i], it.q, it.vcell, i * RS);
+    } else {
+        float gv[N];
+        load_run<N>(gv, rg, reread(it.vcell), 0, RS);
+#pragma unroll
+        for (int i = 0; i < N; ++i) bstore(__builtin_fmaf(dt, acc[i], gv[i]), it.q, it.vcell, i * RS);
+    }
+}
+
+
 // Sum of a double over the n lanes of an aligned lane group.
 template <int N>
 __device__ __forceinline__ double group_sumd(double v)

@@ -322,6 +322,136 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 }
 
 
+// z = alpha ghat + i alpha' fhat for one direction of the bilinear operator
+// (spectral layout as job3d_multiply; chunks of C elements, each chunk's reads
+// issued before their use).
+template <int N, int T, int Q, int C>
+__device__ __forceinline__ void job3d_multiply_bilinear(float2 (&z)[Q][N], rsrc_t rgs, rsrc_t rfs, const DevPlan& pl,
+                                                        const JobDesc& J, int jb, const float* atab, int tid)
+{
+    constexpr int NN = N * N, RS = NN * 4;
+    const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+        const HalfSpec<N, N * N * 8> gs = half3d<N>(rgs, pi);
+        const HalfSpec<N, N * N * 8> fs = half3d<N>(rfs, pi);
+        RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
+#pragma unroll
+        for (int k0 = 0; k0 < N; k0 += C) {
+            float2 G[C], F[C];
+            float a2[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                G[i] = gs.get(k0 + i);
+                F[i] = fs.get(k0 + i);
+                a2[i] = bload(rap, pi * 4, (k0 + i) * RS);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const float al = a.get();
+                z[q][k0 + i] = make_float2(__builtin_fmaf(al, G[i].x, -a2[i] * F[i].y),
+                                           __builtin_fmaf(al, G[i].y, a2[i] * F[i].x));
+                a.next();
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// Bilinear operator Q(g, f) of one 3D cell (see cell2d_eval_bilinear): the
+// transforms of g and f as half spectra in rgh and cl.fh, one inverse
+// transform of alpha_p ghat + i alpha'_p fhat per direction, loss
+// -g IFFT(Lambda fhat).  cl.f holds f, rg holds g; the Euler form updates g.
+// dirw: per-direction weights / n^6.  LACC as in cell3d_eval.
+template <int N, int T, int RV, int LACC = 0>
+__device__ __forceinline__ void cell3d_eval_bilinear(const DevPlan& pl, const Cell3D& cl, rsrc_t rg, rsrc_t rgh,
+                                                     rsrc_t rlam, const float* __restrict__ dirw, float dt,
+                                                     float* xb, const float* dtab, int tid, float* lacc)
+{
+    constexpr int NN = N * N, Q = NN / T, RS = NN * 4, NR = N - LACC;
+    float2 z[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(rg, (tid + q * T) * 4, x * RS), 0.f);
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) half3d<N>(rgh, tid + q * T).put(z[q]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
+    fwd3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
+    float acc[Q][NR > 0 ? NR : 1];
+    auto lslot = [&](int q, int x) -> float& { return lacc[(x - NR) * (T * Q) + tid + q * T]; };
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k0 = 0; k0 < N; k0 += 8) {
+            float l[8];
+            load_run<8>(l, rlam, (tid + q * T) * 4, k0, RS);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                z[q][k0 + k].x *= l[k];
+                z[q][k0 + k].y *= l[k];
+            }
+        }
+    inv3d<N, T, Q, RV>(z, xb, tid);
+    {
+        constexpr int C = N % 8 == 0 ? 8 : N;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x0 = 0; x0 < N; x0 += C) {
+                float gv[C];
+                load_run<C>(gv, rg, (tid + q * T) * 4, x0, RS);
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const int x = x0 + i;
+                    const float v = -gv[i] * z[q][x].x;
+                    if (x < NR) acc[q][x] = v;
+                    else lslot(q, x) = v;
+                }
+            }
+    }
+    // the directions read mirrored pencils of both spectra, written by other threads
+    __syncthreads();
+
+    const float* atab = dtab_alpha(dtab, pl);
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(dirw, J.p);
+        job3d_multiply_bilinear<N, T, Q, (N == 32 && Q == 1) ? 2 : 8>(z, rgh, cl.fh, pl, J, jb, atab, tid);
+        inv3d<N, T, Q, RV>(z, xb, tid);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int x = 0; x < N; ++x) {
+                if (x < NR) acc[q][x] = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, acc[q][x]);
+                else lslot(q, x) = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, lslot(q, x));
+            }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int v = (tid + q * T) * 4;
+        if (dt == 0.f) {
+#pragma unroll
+            for (int x = 0; x < N; ++x) bstore(x < NR ? acc[q][x] : lslot(q, x), cl.q, v, x * RS);
+        } else {
+            float gv[N];
+            load_run<N>(gv, rg, v, 0, RS);
+#pragma unroll
+            for (int x = 0; x < N; ++x)
+                bstore(__builtin_fmaf(dt, x < NR ? acc[q][x] : lslot(q, x), gv[x]), cl.q, v, x * RS);
+        }
+    }
+}
+
+
 // Block-wide sum of five doubles (moments); every thread gets the totals.
 template <int T>
 __device__ __forceinline__ void block_sum5d(double (&v)[5], double* red, int tid)

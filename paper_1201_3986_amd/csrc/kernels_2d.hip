@@ -136,6 +136,39 @@ __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const floa
     }
 }
 
+// Bilinear Q(g, f): 256 threads, 256/n cells per workgroup item, persistent
+// over items; spec holds the transforms of f, spec2 those of g.  At least two
+// waves per SIMD: left alone, one radix order at n = 64 takes two registers
+// beyond the 256 of that occupancy.
+template <int N, int RV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_eval2d_bil(DevPlan pl, int batch, const float* g, const float* f,
+                                                    float* q, float dt, DevScratch s)
+{
+    constexpr int CPW = 64 / N, CPB = 4 * CPW, SLOT = N * (N + 1), NPTS = N * N;
+    extern __shared__ float smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = lane % N, local = wave * CPW + lane / N;
+    float* xb = smem + local * SLOT;
+    float* dtab = smem + CPB * SLOT;
+    load_dtab(dtab, pl, tid, blockDim.x);
+    __syncthreads();
+    const int nitems = (batch + CPB - 1) / CPB;
+    const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
+    Item2D it;
+    it.fh = make_rsrc(s.spec + (size_t)blockIdx.x * CPB * NPTS, CPB * NPTS * 8);
+    it.vcell = (local * NPTS + j) * 4;
+    it.vspec = (local * NPTS + j) * 8;
+    const rsrc_t rgh = make_rsrc(s.spec2 + (size_t)blockIdx.x * CPB * NPTS, CPB * NPTS * 8);
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int first = item * CPB;
+        const int nvalid = min(CPB, batch - first);
+        it.f = make_rsrc(f + (size_t)first * NPTS, nvalid * NPTS * 4);
+        it.q = make_rsrc(q + (size_t)first * NPTS, nvalid * NPTS * 4);
+        const rsrc_t rg = make_rsrc(g + (size_t)first * NPTS, nvalid * NPTS * 4);
+        cell2d_eval_bilinear<N, RV>(pl, it, rg, rgh, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
+    }
+}
+
 // ------------------------------------------------------------------ dispatch
 namespace {
 template <int N>
@@ -194,6 +227,33 @@ hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q,
             if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
             else hipLaunchKernelGGL((k_eval2d<N, 0, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
         }
+    });
+    return hipGetLastError();
+}
+
+hipError_t bil2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid)
+{
+    hipError_t e = hipSuccess;
+    QDVM_SWITCH_2D(pl.n, {
+        li.block = 256;
+        li.lds = lds2d<N>(pl.ntilde);
+        const int items = (batch + 256 / N - 1) / (256 / N);
+        e = variant ? occupancy_grid(k_eval2d_bil<N, 1>, 256, li.lds, items, li.grid)
+                    : occupancy_grid(k_eval2d_bil<N, 0>, 256, li.lds, items, li.grid);
+        if (max_grid > 0) li.grid = std::min(li.grid, max_grid);
+        li.slots = li.grid * (256 / N);
+    });
+    return e;
+}
+
+hipError_t launch_bil2d(const DevPlan& pl, int batch, const float* g, const float* f, float* q, float dt,
+                        DevScratch s, const LaunchInfo& li, int variant, hipStream_t st)
+{
+    QDVM_SWITCH_2D(pl.n, {
+        if (variant)
+            hipLaunchKernelGGL((k_eval2d_bil<N, 1>), dim3(li.grid), dim3(256), li.lds, st, pl, batch, g, f, q, dt, s);
+        else
+            hipLaunchKernelGGL((k_eval2d_bil<N, 0>), dim3(li.grid), dim3(256), li.lds, st, pl, batch, g, f, q, dt, s);
     });
     return hipGetLastError();
 }

@@ -100,6 +100,32 @@ __global__ __launch_bounds__(T) void k_vjp3d(DevPlan pl, int batch, const float*
     }
 }
 
+// Bilinear Q(g, f): one cell per workgroup, persistent over cells; spec holds
+// the transforms of f, spec2 those of g.
+template <int N, int T, int RV>
+__global__ __launch_bounds__(T) void k_eval3d_bil(DevPlan pl, int batch, const float* g, const float* f, float* q,
+                                                  float dt, DevScratch s)
+{
+    constexpr int NN = N * N, NPTS = NN * N;
+    extern __shared__ float smem[];
+    float* xb = smem;
+    float* dtab = smem + N * N * (N + 1);
+    const int tid = threadIdx.x;
+    load_dtab(dtab, pl, tid, T);
+    __syncthreads();
+    const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
+    const rsrc_t rgh = make_rsrc(s.spec2 + (size_t)blockIdx.x * NPTS, NPTS * 8);
+    Cell3D cl;
+    cl.fh = make_rsrc(s.spec + (size_t)blockIdx.x * NPTS, NPTS * 8);
+    for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
+        cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
+        cl.q = make_rsrc(q + (size_t)cell * NPTS, NPTS * 4);
+        const rsrc_t rg = make_rsrc(g + (size_t)cell * NPTS, NPTS * 4);
+        cell3d_eval_bilinear<N, T, RV, lacc3d<N, T>()>(pl, cl, rg, rgh, rlam, s.jobw, dt, xb, dtab, tid,
+                                                       dtab + dtab_floats(pl));
+    }
+}
+
 // ------------------------------------------------------------------ direction-split launches
 // When a batch has fewer cells than the GPU has workgroup slots, the direction
 // loop of each cell is spread over G workgroups (workgroup b: cell b / G, jobs
@@ -205,6 +231,49 @@ __global__ void k_prep(DevPlan pl, const float* __restrict__ w, float* __restric
             ap = pl.aperp[(size_t)jb * npts + idx];
         }
         acc += W * al * ap;
+    }
+    lam[idx] = (float)(acc * inv);
+}
+
+// The bilinear operator's multipliers: Lambda / n^d summed over the directions
+// one by one (a 2D pair (e, e_perp) contributes w_e (a - 1) b + w_perp (b - 1) a
+// with a = D_M(e.K), b = D_M(e_perp.K)) and the per-direction weights w_p / n^{2d}.
+__global__ void k_prep_bil(DevPlan pl, const float* __restrict__ w, float* __restrict__ lam,
+                           float* __restrict__ dirw)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = pl.n, npts = pl.npts;
+    const double inv = 1.0 / (double)npts;
+    if (idx < pl.P) dirw[idx] = (float)((double)w[idx] * inv * inv);
+    if (idx >= npts) return;
+    int K[3];
+    if (pl.dim == 2) {
+        K[1] = idx / n;
+        K[0] = idx % n;
+        K[2] = 0;
+    } else {
+        K[2] = idx / (n * n);
+        const int pi = idx % (n * n);
+        K[0] = pi / n;
+        K[1] = pi % n;
+    }
+    double acc = 0.0;
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = pl.jobs[jb];
+        int sd = J.e[0] * K[0] + J.e[1] * K[1] + J.e[2] * K[2];
+        sd %= n;
+        if (sd < 0) sd += n;
+        const double a = (double)pl.dirichlet[J.M * n + sd];
+        if (pl.dim == 2) {
+            int t = -J.e[1] * K[0] + J.e[0] * K[1];
+            t %= n;
+            if (t < 0) t += n;
+            const double b = pl.dirichlet[J.M * n + t];
+            acc += (double)w[J.p] * (a - 1.0) * b;
+            if (J.pp >= 0) acc += (double)w[J.pp] * (b - 1.0) * a;
+        } else {
+            acc += (double)w[J.p] * (a - 1.0) * pl.aperp[(size_t)jb * npts + idx];
+        }
     }
     lam[idx] = (float)(acc * inv);
 }
@@ -355,6 +424,53 @@ hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, f
     return hipGetLastError();
 }
 
+hipError_t launch_prep_bilinear(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st)
+{
+    const int threads = 256;
+    const int n = std::max(pl.npts, pl.P);
+    hipLaunchKernelGGL(k_prep_bil, dim3((n + threads - 1) / threads), dim3(threads), 0, st, pl, w, s.lam, s.jobw);
+    return hipGetLastError();
+}
+
+LaunchInfo bilinear_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim)
+{
+    LaunchInfo li;
+    hipError_t e = hipSuccess;
+    if (pl.dim == 2) {
+        e = bil2d_info(pl, batch, variant, li, lim.max_grid);
+    } else {
+        auto body = [&]() -> hipError_t {
+            QDVM_SWITCH_3D(pl.n, {
+                constexpr int T = t3d<N>();
+                li.block = T;
+                li.lds = lds3d<N, T>(pl.ntilde);
+                e = variant ? occupancy_grid(k_eval3d_bil<N, T, 1>, T, li.lds, batch, li.grid)
+                            : occupancy_grid(k_eval3d_bil<N, T, 0>, T, li.lds, batch, li.grid);
+                if (lim.max_grid > 0) li.grid = std::min(li.grid, lim.max_grid);
+                li.slots = li.grid;
+            });
+            return e;
+        };
+        e = body();
+    }
+    if (e != hipSuccess) li.grid = 0;
+    return li;
+}
+
+hipError_t launch_eval_bilinear(const DevPlan& pl, int batch, const float* g, const float* f, float* q, float dt,
+                                DevScratch s, const LaunchInfo& li, int variant, hipStream_t st)
+{
+    if (pl.dim == 2) return launch_bil2d(pl, batch, g, f, q, dt, s, li, variant, st);
+    QDVM_SWITCH_3D(pl.n, {
+        constexpr int T = t3d<N>();
+        if (variant)
+            hipLaunchKernelGGL((k_eval3d_bil<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, g, f, q, dt, s);
+        else
+            hipLaunchKernelGGL((k_eval3d_bil<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, g, f, q, dt, s);
+    });
+    return hipGetLastError();
+}
+
 LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim)
 {
     LaunchInfo li;
@@ -389,10 +505,11 @@ LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimi
 int max_slots(const DevPlan& pl, int op, int variant)
 {
     const int big = 1 << 28;
-    const LaunchInfo li = op == 0 ? eval_launch_info(pl, big, variant) : vjp_launch_info(pl, big, variant);
+    const LaunchInfo li = op == 0 ? eval_launch_info(pl, big, variant)
+                                  : (op == 1 ? vjp_launch_info(pl, big, variant) : bilinear_launch_info(pl, big, variant));
     if (li.grid <= 0) return 0;
     int slots = li.slots;
-    if (pl.dim == 3 && !(op == 0 && pl.mode)) {
+    if (pl.dim == 3 && op != 2 && !(op == 0 && pl.mode)) {
         // direction-split launches: one slot per workgroup, up to the split kernel's occupancy
         int cap = 0;
         hipError_t e = hipSuccess;

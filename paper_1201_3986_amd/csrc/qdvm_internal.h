@@ -33,6 +33,8 @@ struct DevPlan {
     const int32_t* dir_job;      // [P] job holding each direction, -1 if M_p = 0
     const float* lam0;           // [npts] Lambda / npts for the default weights
     const float* jobw0;          // [njobs] job weights / npts^2 for the default weights
+    const float* lamb0;          // [npts] Lambda / npts of the bilinear operator (directions unpaired)
+    const float* dirw0;          // [P] direction weights / npts^2 for the default weights
 };
 
 // Per-call scratch carved out of a plan's workspace.
@@ -66,6 +68,8 @@ struct HostPlan {
     int32_t* d_dir_job = nullptr;
     float* d_lam0 = nullptr;
     float* d_jobw0 = nullptr;
+    float* d_lamb0 = nullptr;
+    float* d_dirw0 = nullptr;
     std::vector<int32_t> dir_job;    // P
     int device = 0;
     // workspace, allocated with the plan and sized for every batch (max_slots)
@@ -82,6 +86,8 @@ struct HostPlan {
         d.dir_job = d_dir_job;
         d.lam0 = d_lam0;
         d.jobw0 = d_jobw0;
+        d.lamb0 = d_lamb0;
+        d.dirw0 = d_dirw0;
         return d;
     }
 };
@@ -115,8 +121,17 @@ LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant, LaunchLim
 hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, float dt,
                        DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
 LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim = LaunchLimits());
+// Bilinear Q(g, f) (kernels_3d.hip and kernels_2d.hip): multipliers into
+// s.lam (Lambda of the unpaired directions) and s.jobw (P direction weights).
+hipError_t launch_prep_bilinear(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st);
+LaunchInfo bilinear_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim = LaunchLimits());
+hipError_t launch_eval_bilinear(const DevPlan& pl, int batch, const float* g, const float* f, float* q, float dt,
+                                DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
+hipError_t bil2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid);
+hipError_t launch_bil2d(const DevPlan& pl, int batch, const float* g, const float* f, float* q, float dt,
+                        DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
 // Largest number of resident cell slots any batch can use with the kernels of
-// op (0: evaluation, 1: adjoint) and variant, direction-split launches
+// op (0: evaluation, 1: adjoint, 2: bilinear evaluation) and variant, direction-split launches
 // included: it bounds the spectral scratch, the grad_w partial rows and the
 // split parts, so a plan's workspace can be sized once for every batch.
 int max_slots(const DevPlan& pl, int op, int variant);

@@ -64,6 +64,7 @@ def load():
             "qdvm_eval": [vp, i32, vp, vp, vp, ctypes.c_float, vp],
             "qdvm_vjp": [vp, i32, vp, vp, vp, vp, vp, vp],
             "qdvm_eval_noalloc": [vp, i32, vp, vp, vp, ctypes.c_float, vp],
+            "qdvm_eval_bilinear": [vp, i32, vp, vp, vp, vp, ctypes.c_float, vp],
             "qdvm_set_variant": [vp, i32, i32],
             "qdvm_get_variant": [vp, i32, i32p],
             "qdvm_autotune": [vp, i32, vp],
@@ -224,6 +225,21 @@ class Plan:
             raise ValueError("out and f differ in size")
         w = self._weights(w)
         _check(load().qdvm_eval(self._h, batch, _ptr(f), _ptr(out), _ptr(w), float(dt), _stream_ptr(stream)))
+        return out
+
+    def eval_bilinear(self, g, f, out=None, w=None, dt=0.0, stream=None):
+        """Q(g, f) (dt == 0) or g + dt Q(g, f) for every cell; out may be g or f."""
+        import torch
+        batch = self._cells(g, "g")
+        if self._cells(f, "f") != batch:
+            raise ValueError("g and f differ in size")
+        if out is None:
+            out = torch.empty_like(g)
+        elif self._cells(out, "out") != batch:
+            raise ValueError("out and g differ in size")
+        w = self._weights(w)
+        _check(load().qdvm_eval_bilinear(self._h, batch, _ptr(g), _ptr(f), _ptr(out), _ptr(w), float(dt),
+                                         _stream_ptr(stream)))
         return out
 
     def eval_noalloc(self, f, out, w=None, dt=0.0, stream=None):
