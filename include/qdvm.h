@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define QDVM_ABI_VERSION 3
+#define QDVM_ABI_VERSION 4
 
 typedef enum {
     QDVM_OK = 0,
@@ -76,10 +76,30 @@ typedef struct {
                                (|e|_inf, then |e|_2^2, then components ascending) */
     const int32_t* dirs;    /* optional host array P x d: primitive vectors, first nonzero
                                component positive, no two on the same line */
-    const double* weights;  /* optional host array of P weights; NULL selects
-                               a(k) = h^(2d-1) |e_p|_2 (Sec. 3.2, after eq. (3.3)) */
+    const double* weights;  /* optional host array of P weights w_p; NULL selects the profile's
+                               default (below) */
     int32_t mode;           /* QDVM_MODE_FULL or QDVM_MODE_NEAR_EQUILIBRIUM (below) */
+    int32_t line_weight;    /* weight a(k) of the points k = m e_p of a line (below) */
 } qdvm_desc;
+
+/*
+ * Line-weight profiles: the factor a(k) of the decoupled kernel a(k) b(l),
+ * b = 1 (Sec. 3.2, eq. (3.3)), at the points k = m e_p, 0 < |m| <= M_p.
+ *   QDVM_LINE_UNIFORM: a(m e_p) = w_p, the paper's lattice weights
+ *     a(k) = h^(2d-1) |k| / gcd(k) = h^(2d-1) |e_p|_2 (Sec. 3.2, after
+ *     eq. (3.3)) by default.  2D perpendicular lines share a transform.
+ *   QDVM_LINE_DELTA: a(m e_p) = w_p / |m| with default w_p = h^(2d-2), i.e.
+ *     a(k) = h^(2d-2) / gcd(k): the lattice quadrature of delta(x . y) in the
+ *     Carleman form of Sec. 2.2 for a constant kernel (a point of the line or
+ *     plane orthogonal to k stands for a length or area h^(d-1) |k| / gcd(k),
+ *     divided by |x| = h |k|).  With it the 2D Maxwell-molecule operator
+ *     converges to the BKW solution of Sec. 4 as n grows; the uniform
+ *     profile's operator does not (its continuum limit carries an extra
+ *     factor |x|).  No 2D pairing (the pair's terms differ when the weight
+ *     varies along a line), so P transforms per cell in 2D.
+ */
+#define QDVM_LINE_UNIFORM 0
+#define QDVM_LINE_DELTA 1
 
 /*
  * Evaluation modes.
@@ -106,6 +126,7 @@ typedef struct {
     int32_t num_jobs;       /* inverse transforms per cell in the direction loop */
     double h;
     int32_t mode;           /* the descriptor's evaluation mode */
+    int32_t line_weight;    /* the descriptor's line-weight profile */
 } qdvm_plan_info_t;
 
 /* Build a plan: direction set, line lengths M_p, weights and FP64-built

@@ -8,7 +8,9 @@ parameters the paper fixes:
   per line with its first nonzero component positive (Sec. 3.2, Farey series
   and the set A^{d-1}), listed by (|e|_inf, |e|_2^2, lexicographic);
 * default weights a(k) = h^(2d-1) |k| / gcd(k), b = 1 (Sec. 3.2, after
-  eq. (3.3)), which is h^(2d-1) |e_p|_2 on the line of e_p;
+  eq. (3.3)), which is h^(2d-1) |e_p|_2 on the line of e_p; or, with the delta
+  line-weight profile, a(k) = h^(2d-2) / gcd(k) (w_p = h^(2d-2), the point
+  k = m e_p weighted by 1/|m|);
 * default truncation Nt = floor(n / (3 + sqrt 2)) (Sec. 4, the choice of Nt
   next to Table 1; the printed values 1, 3, 7, 14 for 8, 16, 32, 64 points).
 """
@@ -53,11 +55,12 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         lib.oracle_lines.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int]
         lib.oracle_lines.restype = ctypes.c_int
-        lib.oracle_default_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, i32p, dp]
-        lib.oracle_collide.argtypes = [ctypes.c_int] * 4 + [i32p, dp, ctypes.c_int, dp, dp]
-        lib.oracle_collide_terms.argtypes = [ctypes.c_int] * 4 + [i32p, dp, dp]
-        lib.oracle_collide_bilinear.argtypes = [ctypes.c_int] * 4 + [i32p, dp, ctypes.c_int, dp, dp, dp]
-        lib.oracle_vjp.argtypes = [ctypes.c_int] * 4 + [i32p, dp, ctypes.c_int, dp, dp, dp, dp]
+        lib.oracle_default_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, i32p, ctypes.c_int, dp]
+        ci = ctypes.c_int
+        lib.oracle_collide.argtypes = [ci] * 4 + [i32p, dp, ci, ci, dp, dp]
+        lib.oracle_collide_terms.argtypes = [ci] * 4 + [i32p, ci, dp, dp]
+        lib.oracle_collide_bilinear.argtypes = [ci] * 4 + [i32p, dp, ci, ci, dp, dp, dp]
+        lib.oracle_vjp.argtypes = [ci] * 4 + [i32p, dp, ci, ci, dp, dp, dp, dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -97,11 +100,11 @@ def first_lines(d: int, count: int) -> np.ndarray:
         order += 1
 
 
-def default_weights(d: int, h: float, dirs) -> np.ndarray:
+def default_weights(d: int, h: float, dirs, line_weight: int = 0) -> np.ndarray:
     lib = _load()
     dirs, dptr = _i32(dirs)
     w = np.zeros(len(dirs), dtype=np.float64)
-    lib.oracle_default_weights(d, float(h), len(dirs), dptr,
+    lib.oracle_default_weights(d, float(h), len(dirs), dptr, int(line_weight),
                                w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return w
 
@@ -118,20 +121,21 @@ def _cells(f, d, n):
     return np.ascontiguousarray(f), f.size // npts
 
 
-def collide(d, n, ntilde, dirs, w, f) -> np.ndarray:
-    """Q(f, f) by direct summation; f has shape (..., n, ..., n) or (batch*n^d,)."""
+def collide(d, n, ntilde, dirs, w, f, line_weight=0) -> np.ndarray:
+    """Q(f, f) by direct summation; f has shape (..., n, ..., n) or (batch*n^d,).
+    line_weight 1: the term of k = m e_p carries w_p / |m| (delta quadrature)."""
     lib = _load()
     f, batch = _cells(f, d, n)
     dirs, dptr = _i32(dirs)
     w, wptr = _f64(w)
     q = np.zeros_like(f)
-    lib.oracle_collide(d, n, ntilde, len(dirs), dptr, wptr, batch,
+    lib.oracle_collide(d, n, ntilde, len(dirs), dptr, wptr, int(line_weight), batch,
                        f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return q
 
 
-def collide_bilinear(d, n, ntilde, dirs, w, g, f) -> np.ndarray:
+def collide_bilinear(d, n, ntilde, dirs, w, g, f, line_weight=0) -> np.ndarray:
     """Q(g, f) by direct summation (gain g(i+k) f(i+l), loss g(i) f(i+k+l));
     g and f of the same shape, one or more cells."""
     lib = _load()
@@ -143,12 +147,12 @@ def collide_bilinear(d, n, ntilde, dirs, w, g, f) -> np.ndarray:
     w, wptr = _f64(w)
     q = np.zeros_like(f)
     P = ctypes.POINTER(ctypes.c_double)
-    lib.oracle_collide_bilinear(d, n, ntilde, len(dirs), dptr, wptr, batch, g.ctypes.data_as(P),
+    lib.oracle_collide_bilinear(d, n, ntilde, len(dirs), dptr, wptr, int(line_weight), batch, g.ctypes.data_as(P),
                                 f.ctypes.data_as(P), q.ctypes.data_as(P))
     return q
 
 
-def collide_terms(d, n, ntilde, dirs, f) -> np.ndarray:
+def collide_terms(d, n, ntilde, dirs, f, line_weight=0) -> np.ndarray:
     """Unit-weight per-direction contributions Q_p for one cell, shape (P, n^d)."""
     lib = _load()
     f, batch = _cells(f, d, n)
@@ -156,13 +160,13 @@ def collide_terms(d, n, ntilde, dirs, f) -> np.ndarray:
         raise ValueError("collide_terms takes one cell")
     dirs, dptr = _i32(dirs)
     out = np.zeros((len(dirs), n ** d), dtype=np.float64)
-    lib.oracle_collide_terms(d, n, ntilde, len(dirs), dptr,
+    lib.oracle_collide_terms(d, n, ntilde, len(dirs), dptr, int(line_weight),
                              f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
 
 
-def vjp(d, n, ntilde, dirs, w, f, c):
+def vjp(d, n, ntilde, dirs, w, f, c, line_weight=0):
     """(grad_f, grad_w) of <c, Q(f; w)>; grad_w summed over cells."""
     lib = _load()
     f, batch = _cells(f, d, n)
@@ -174,7 +178,7 @@ def vjp(d, n, ntilde, dirs, w, f, c):
     gf = np.zeros_like(f)
     gw = np.zeros(len(dirs), dtype=np.float64)
     P = ctypes.POINTER(ctypes.c_double)
-    lib.oracle_vjp(d, n, ntilde, len(dirs), dptr, wptr, batch, f.ctypes.data_as(P),
+    lib.oracle_vjp(d, n, ntilde, len(dirs), dptr, wptr, int(line_weight), batch, f.ctypes.data_as(P),
                    c.ctypes.data_as(P), gf.ctypes.data_as(P), gw.ctypes.data_as(P))
     return gf, gw
 
@@ -240,7 +244,7 @@ def adaptive_levels(r, thresholds) -> np.ndarray:
     return np.array([int(np.sum(x > t)) for x in np.ravel(r)], dtype=np.int32)
 
 
-def collide_near_equilibrium(d, n, ntilde, dirs, w, f) -> np.ndarray:
+def collide_near_equilibrium(d, n, ntilde, dirs, w, f, line_weight=0) -> np.ndarray:
     """Q(f, f) - Q(M, M) with M = index_maxwellian(f), both by direct summation."""
     M = index_maxwellian(d, n, f)
-    return collide(d, n, ntilde, dirs, w, f) - collide(d, n, ntilde, dirs, w, M)
+    return collide(d, n, ntilde, dirs, w, f, line_weight) - collide(d, n, ntilde, dirs, w, M, line_weight)

@@ -26,7 +26,10 @@
  *
  *   M_p = floor(Nt / |e_p|_inf),   L_p = { l in Z^d : l.e_p = 0, |l|_inf <= Nt },
  *
- * on the periodic lattice (Z/nZ)^d (indices wrap mod n, Sec. 2.3).  The
+ * on the periodic lattice (Z/nZ)^d (indices wrap mod n, Sec. 2.3).  Every
+ * function also takes a line-weight profile: with line_weight = 1 the term of
+ * k = m e_p carries w_p / |m| instead of w_p (a(k) = h^(2d-2)/gcd(k), the
+ * lattice quadrature of delta(x . y) for a constant kernel).  The
  * vector-Jacobian product of Q with respect to f and to the weights w_p is
  * obtained by differentiating that sum term by term.
  *
@@ -128,13 +131,14 @@ int oracle_lines(int d, int order, int32_t *out, int cap)
  * (h^5 for 3D hard spheres, h^3 for 2D Maxwell molecules), with |k| measured
  * in lattice units.  For k = m e_p this is h^(2d-1) |e_p|_2 on the whole line.
  */
-void oracle_default_weights(int d, double h, int P, const int32_t *dirs, double *w)
+void oracle_default_weights(int d, double h, int P, const int32_t *dirs, int line_weight, double *w)
 {
+    /* uniform profile: h^(2d-1) |e_p|_2; delta profile: h^(2d-2) (then a(m e_p) = w_p / |m|) */
     double s = pow(h, 2 * d - 1);
     for (int p = 0; p < P; ++p) {
         double n2 = 0.0;
         for (int a = 0; a < d; ++a) n2 += (double)dirs[p * d + a] * dirs[p * d + a];
-        w[p] = s * sqrt(n2);
+        w[p] = line_weight ? pow(h, 2 * d - 2) : s * sqrt(n2);
     }
 }
 
@@ -145,20 +149,29 @@ void oracle_default_weights(int d, double h, int P, const int32_t *dirs, double 
 typedef struct {
     int nk, nl;
     int *k;     /* nk x d : m e_p, 0 < |m| <= M_p      */
+    double *kw; /* nk     : weight factor of k = m e_p: 1 (uniform), 1/|m| (delta) */
     int *l;     /* nl x d : l.e_p = 0, |l|_inf <= Nt    */
 } or_sets;
 
-static void or_build_sets(int d, int ntilde, const int32_t *e, or_sets *s)
+/*
+ * Line-weight profile: a(k) for k = m e_p is w_p (line_weight 0, the paper's
+ * lattice weight h^(2d-1)|k|/gcd(k), constant along a line) or w_p / |m|
+ * (line_weight 1: the lattice quadrature of delta(x . y) for a constant
+ * kernel, h^(2d-2)/gcd(k) with gcd(m e_p) = |m|).
+ */
+static void or_build_sets(int d, int ntilde, const int32_t *e, int line_weight, or_sets *s)
 {
     int ninf = 0;
     for (int a = 0; a < d; ++a) if (or_abs(e[a]) > ninf) ninf = or_abs(e[a]);
     int M = ninf > 0 ? ntilde / ninf : 0;
     s->nk = 2 * M;
     s->k = (int *)malloc(sizeof(int) * (size_t)(s->nk > 0 ? s->nk : 1) * d);
+    s->kw = (double *)malloc(sizeof(double) * (size_t)(s->nk > 0 ? s->nk : 1));
     int c = 0;
     for (int m = -M; m <= M; ++m) {
         if (m == 0) continue;
         for (int a = 0; a < d; ++a) s->k[c * d + a] = m * e[a];
+        s->kw[c] = line_weight ? 1.0 / (double)or_abs(m) : 1.0;
         ++c;
     }
     int side = 2 * ntilde + 1, total = 1;
@@ -175,7 +188,7 @@ static void or_build_sets(int d, int ntilde, const int32_t *e, or_sets *s)
     }
 }
 
-static void or_free_sets(or_sets *s) { free(s->k); free(s->l); }
+static void or_free_sets(or_sets *s) { free(s->k); free(s->kw); free(s->l); }
 
 /* flat index of (i + o) on the periodic grid, i given by its coordinates */
 static inline long or_wrap(int d, int n, const int *i, const int *o1, const int *o2)
@@ -210,13 +223,13 @@ static long or_npts(int d, int n)
  * Unit-weight contribution of each direction, Q_p (so that Q = sum_p w_p Q_p),
  * for one cell: qp[p * n^d + i].
  */
-void oracle_collide_terms(int d, int n, int ntilde, int P, const int32_t *dirs,
+void oracle_collide_terms(int d, int n, int ntilde, int P, const int32_t *dirs, int line_weight,
                           const double *f, double *qp)
 {
     long npts = or_npts(d, n);
     for (int p = 0; p < P; ++p) {
         or_sets s;
-        or_build_sets(d, ntilde, dirs + (size_t)p * d, &s);
+        or_build_sets(d, ntilde, dirs + (size_t)p * d, line_weight, &s);
         double *out = qp + (size_t)p * npts;
 #pragma omp parallel for schedule(static)
         for (long flat = 0; flat < npts; ++flat) {
@@ -230,7 +243,7 @@ void oracle_collide_terms(int d, int n, int ntilde, int P, const int32_t *dirs,
                     const int *l = s.l + (size_t)b * d;
                     long il = or_wrap(d, n, i, l, NULL);
                     long ikl = or_wrap(d, n, i, k, l);
-                    acc += f[ik] * f[il] - f[flat] * f[ikl];
+                    acc += s.kw[a] * (f[ik] * f[il] - f[flat] * f[ikl]);
                 }
             }
             out[flat] = acc;
@@ -240,12 +253,12 @@ void oracle_collide_terms(int d, int n, int ntilde, int P, const int32_t *dirs,
 }
 
 /* Q = sum_p w_p Q_p for `batch` cells stored one after another. */
-void oracle_collide(int d, int n, int ntilde, int P, const int32_t *dirs, const double *w,
+void oracle_collide(int d, int n, int ntilde, int P, const int32_t *dirs, const double *w, int line_weight,
                     int batch, const double *f, double *q)
 {
     long npts = or_npts(d, n);
     or_sets *s = (or_sets *)malloc(sizeof(or_sets) * (size_t)(P > 0 ? P : 1));
-    for (int p = 0; p < P; ++p) or_build_sets(d, ntilde, dirs + (size_t)p * d, &s[p]);
+    for (int p = 0; p < P; ++p) or_build_sets(d, ntilde, dirs + (size_t)p * d, line_weight, &s[p]);
     for (int cell = 0; cell < batch; ++cell) {
         const double *fc = f + (size_t)cell * npts;
         double *qc = q + (size_t)cell * npts;
@@ -263,7 +276,7 @@ void oracle_collide(int d, int n, int ntilde, int P, const int32_t *dirs, const 
                         const int *l = s[p].l + (size_t)b * d;
                         long il = or_wrap(d, n, i, l, NULL);
                         long ikl = or_wrap(d, n, i, k, l);
-                        acc += fc[ik] * fc[il] - fc[flat] * fc[ikl];
+                        acc += s[p].kw[a] * (fc[ik] * fc[il] - fc[flat] * fc[ikl]);
                     }
                 }
                 total += w[p] * acc;
@@ -286,11 +299,11 @@ void oracle_collide(int d, int n, int ntilde, int P, const int32_t *dirs, const 
  * Q(f, f) is the diagonal.  Same sets and weights as oracle_collide.
  */
 void oracle_collide_bilinear(int d, int n, int ntilde, int P, const int32_t *dirs, const double *w,
-                             int batch, const double *g, const double *f, double *q)
+                             int line_weight, int batch, const double *g, const double *f, double *q)
 {
     long npts = or_npts(d, n);
     or_sets *s = (or_sets *)malloc(sizeof(or_sets) * (size_t)(P > 0 ? P : 1));
-    for (int p = 0; p < P; ++p) or_build_sets(d, ntilde, dirs + (size_t)p * d, &s[p]);
+    for (int p = 0; p < P; ++p) or_build_sets(d, ntilde, dirs + (size_t)p * d, line_weight, &s[p]);
     for (int cell = 0; cell < batch; ++cell) {
         const double *gc = g + (size_t)cell * npts;
         const double *fc = f + (size_t)cell * npts;
@@ -309,7 +322,7 @@ void oracle_collide_bilinear(int d, int n, int ntilde, int P, const int32_t *dir
                         const int *l = s[p].l + (size_t)b * d;
                         long il = or_wrap(d, n, i, l, NULL);
                         long ikl = or_wrap(d, n, i, k, l);
-                        acc += gc[ik] * fc[il] - gc[flat] * fc[ikl];
+                        acc += s[p].kw[a] * (gc[ik] * fc[il] - gc[flat] * fc[ikl]);
                     }
                 }
                 total += w[p] * acc;
@@ -331,12 +344,12 @@ void oracle_collide_bilinear(int d, int n, int ntilde, int P, const int32_t *dir
  * (each bracket f_a f_b - f_c f_d of the sum differentiated by the index
  * substitution that puts the free index at j).  grad_w is summed over cells.
  */
-void oracle_vjp(int d, int n, int ntilde, int P, const int32_t *dirs, const double *w,
+void oracle_vjp(int d, int n, int ntilde, int P, const int32_t *dirs, const double *w, int line_weight,
                 int batch, const double *f, const double *c, double *grad_f, double *grad_w)
 {
     long npts = or_npts(d, n);
     or_sets *s = (or_sets *)malloc(sizeof(or_sets) * (size_t)(P > 0 ? P : 1));
-    for (int p = 0; p < P; ++p) or_build_sets(d, ntilde, dirs + (size_t)p * d, &s[p]);
+    for (int p = 0; p < P; ++p) or_build_sets(d, ntilde, dirs + (size_t)p * d, line_weight, &s[p]);
     for (int p = 0; p < P; ++p) grad_w[p] = 0.0;
     double *qp = (double *)malloc(sizeof(double) * (size_t)npts * (P > 0 ? P : 1));
     for (int cell = 0; cell < batch; ++cell) {
@@ -364,15 +377,15 @@ void oracle_vjp(int d, int n, int ntilde, int P, const int32_t *dirs, const doub
                         long jmlpk = or_wrap(d, n, j, ml, k);   /* j-l+k */
                         long jpkl = or_wrap(d, n, j, k, l);     /* j+k+l */
                         long jmkml = or_wrap(d, n, j, mk, ml);  /* j-k-l */
-                        acc += cc[jmk] * fc[jmkpl] + cc[jml] * fc[jmlpk]
-                             - cc[flat] * fc[jpkl] - cc[jmkml] * fc[jmkml];
+                        acc += s[p].kw[a] * (cc[jmk] * fc[jmkpl] + cc[jml] * fc[jmlpk]
+                                             - cc[flat] * fc[jpkl] - cc[jmkml] * fc[jmkml]);
                     }
                 }
                 total += w[p] * acc;
             }
             gc[flat] = total;
         }
-        oracle_collide_terms(d, n, ntilde, P, dirs, fc, qp);
+        oracle_collide_terms(d, n, ntilde, P, dirs, line_weight, fc, qp);
         for (int p = 0; p < P; ++p) {
             double acc = 0.0;
             for (long i = 0; i < npts; ++i) acc += cc[i] * qp[(size_t)p * npts + i];

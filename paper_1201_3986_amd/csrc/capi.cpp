@@ -399,7 +399,7 @@ qdvm_status qdvm_plan(const qdvm_desc* desc, qdvm_plan_t* out)
     std::string msg;
     try {
         msg = qdvm::build_host_plan(desc->dim, desc->n, desc->half_width, desc->ntilde, desc->farey_order,
-                                    desc->num_dirs, desc->dirs, desc->weights, p->hp);
+                                    desc->num_dirs, desc->dirs, desc->weights, desc->line_weight, p->hp);
     } catch (const std::bad_alloc&) {
         delete p;
         return fail(QDVM_ENOMEM, "host allocation failed while building the plan");
@@ -471,7 +471,7 @@ qdvm_status qdvm_describe(const qdvm_desc* desc, int32_t* num_dirs, int32_t* dir
     std::string msg;
     try {
         msg = qdvm::build_host_plan(desc->dim, desc->n, desc->half_width, desc->ntilde, desc->farey_order,
-                                    desc->num_dirs, desc->dirs, desc->weights, hp);
+                                    desc->num_dirs, desc->dirs, desc->weights, desc->line_weight, hp);
     } catch (const std::bad_alloc&) {
         return fail(QDVM_ENOMEM, "host allocation failed while building the plan");
     } catch (...) {
@@ -510,6 +510,7 @@ qdvm_status qdvm_plan_info(qdvm_plan_t p, qdvm_plan_info_t* info)
     info->num_jobs = (int32_t)p->hp.jobs.size();
     info->h = p->hp.h;
     info->mode = p->hp.mode;
+    info->line_weight = p->hp.line_weight;
     return QDVM_OK;
 }
 

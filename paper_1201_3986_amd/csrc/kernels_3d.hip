@@ -220,7 +220,7 @@ __global__ void k_prep(DevPlan pl, const float* __restrict__ w, float* __restric
         int sd = J.e[0] * K[0] + J.e[1] * K[1] + J.e[2] * K[2];
         sd %= n;
         if (sd < 0) sd += n;
-        const double al = (double)pl.dirichlet[J.M * n + sd] - 1.0;
+        const double al = (double)pl.dirichlet[(pl.ntilde + 1 + J.M) * n + sd];
         double ap;
         if (pl.dim == 2) {
             int t = -J.e[1] * K[0] + J.e[0] * K[1];
@@ -236,8 +236,8 @@ __global__ void k_prep(DevPlan pl, const float* __restrict__ w, float* __restric
 }
 
 // The bilinear operator's multipliers: Lambda / n^d summed over the directions
-// one by one (a 2D pair (e, e_perp) contributes w_e (a - 1) b + w_perp (b - 1) a
-// with a = D_M(e.K), b = D_M(e_perp.K)) and the per-direction weights w_p / n^{2d}.
+// one by one (a 2D pair (e, e_perp) contributes w_e A_M(e.K) D_M(e_perp.K) +
+// w_perp A_M(e_perp.K) D_M(e.K)) and the per-direction weights w_p / n^{2d}.
 __global__ void k_prep_bil(DevPlan pl, const float* __restrict__ w, float* __restrict__ lam,
                            float* __restrict__ dirw)
 {
@@ -263,16 +263,17 @@ __global__ void k_prep_bil(DevPlan pl, const float* __restrict__ w, float* __res
         int sd = J.e[0] * K[0] + J.e[1] * K[1] + J.e[2] * K[2];
         sd %= n;
         if (sd < 0) sd += n;
-        const double a = (double)pl.dirichlet[J.M * n + sd];
+        const int arow = (pl.ntilde + 1 + J.M) * n;   // line multipliers A_M
         if (pl.dim == 2) {
             int t = -J.e[1] * K[0] + J.e[0] * K[1];
             t %= n;
             if (t < 0) t += n;
-            const double b = pl.dirichlet[J.M * n + t];
-            acc += (double)w[J.p] * (a - 1.0) * b;
-            if (J.pp >= 0) acc += (double)w[J.pp] * (b - 1.0) * a;
+            // line e, plane e_perp; a paired perpendicular takes the two roles exchanged
+            acc += (double)w[J.p] * (double)pl.dirichlet[arow + sd] * (double)pl.dirichlet[J.M * n + t];
+            if (J.pp >= 0)
+                acc += (double)w[J.pp] * (double)pl.dirichlet[arow + t] * (double)pl.dirichlet[J.M * n + sd];
         } else {
-            acc += (double)w[J.p] * (a - 1.0) * pl.aperp[(size_t)jb * npts + idx];
+            acc += (double)w[J.p] * (double)pl.dirichlet[arow + sd] * pl.aperp[(size_t)jb * npts + idx];
         }
     }
     lam[idx] = (float)(acc * inv);

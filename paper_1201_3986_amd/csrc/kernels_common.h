@@ -83,12 +83,9 @@ __device__ __forceinline__ T gload(const T* p, int i)
 __device__ __forceinline__ int dtab_floats(const DevPlan& pl) { return 2 * (pl.ntilde + 1) * pl.n; }
 __device__ __forceinline__ void load_dtab(float* dtab, const DevPlan& pl, int tid, int nthreads)
 {
-    const int m = (pl.ntilde + 1) * pl.n;
-    for (int i = tid; i < m; i += nthreads) {
-        const float d = gload(pl.dirichlet, i);
-        dtab[i] = d;
-        dtab[m + i] = d - 1.f;
-    }
+    // D_M rows (plane multipliers in 2D), then the line multipliers A_M
+    const int m = 2 * (pl.ntilde + 1) * pl.n;
+    for (int i = tid; i < m; i += nthreads) dtab[i] = gload(pl.dirichlet, i);
 }
 __device__ __forceinline__ const float* dtab_alpha(const float* dtab, const DevPlan& pl)
 {

@@ -97,10 +97,12 @@ std::vector<Line> lines_of_order(int dim, int order)
 }  // namespace
 
 std::string build_host_plan(int dim, int n, double half_width, int ntilde, int farey_order,
-                            int num_dirs, const int32_t* dirs, const double* weights, HostPlan& hp)
+                            int num_dirs, const int32_t* dirs, const double* weights, int line_weight, HostPlan& hp)
 {
     char msg[256];
     if (dim != 2 && dim != 3) return "invalid: dim must be 2 or 3";
+    if (line_weight != 0 && line_weight != 1)
+        return "invalid: line_weight must be QDVM_LINE_UNIFORM (0) or QDVM_LINE_DELTA (1)";
     if (n < 2) return "invalid: n must be at least 2";
     if (!supported_size(dim, n)) {
         std::snprintf(msg, sizeof msg, "unsupported: n = %d for dim %d (2D: 8,16,32,64; 3D: 8,16,24,32)", n, dim);
@@ -157,6 +159,7 @@ std::string build_host_plan(int dim, int n, double half_width, int ntilde, int f
 
     hp.dim = dim;
     hp.n = n;
+    hp.line_weight = line_weight;
     hp.ntilde = ntilde;
     hp.half_width = half_width;
     hp.h = 2.0 * half_width / n;
@@ -173,13 +176,17 @@ std::string build_host_plan(int dim, int n, double half_width, int ntilde, int f
             n2 += double(x) * x;
         }
         hp.M.push_back(ntilde / inf);
-        // a(k) = h^(2d-1) |k| / gcd(k) (Sec. 3.2, after eq. (3.3)): constant on a line
-        hp.weights[p] = weights ? weights[p] : std::pow(hp.h, 2 * dim - 1) * std::sqrt(n2);
+        // uniform profile: a(k) = h^(2d-1) |k| / gcd(k) (Sec. 3.2, after eq. (3.3)), constant on
+        // a line; delta profile: a(m e_p) = w_p / |m| with w_p = h^(2d-2), the lattice quadrature
+        // of delta(x . y) for a constant kernel
+        const double wdef = line_weight ? std::pow(hp.h, 2 * dim - 2) : std::pow(hp.h, 2 * dim - 1) * std::sqrt(n2);
+        hp.weights[p] = weights ? weights[p] : wdef;
         if (weights && !std::isfinite(weights[p])) return "invalid: weights must be finite";
     }
 
     // Jobs: one inverse transform per direction with M >= 1; in 2D a direction
-    // and its perpendicular share one.
+    // and its perpendicular share one (their unit-weight terms are equal only
+    // when the weight is uniform along the line, Remark 3.5).
     hp.jobs.clear();
     std::vector<int> used(hp.P, 0);
     for (int p = 0; p < hp.P; ++p) {
@@ -190,7 +197,7 @@ std::string build_host_plan(int dim, int n, double half_width, int ntilde, int f
         j.p = p;
         j.pp = -1;
         used[p] = 1;
-        if (dim == 2) {
+        if (dim == 2 && line_weight == 0) {
             Line perp = {-L[p][1], L[p][0]};
             if (perp[0] < 0 || (perp[0] == 0 && perp[1] < 0)) perp = {L[p][1], -L[p][0]};
             for (int r = p + 1; r < hp.P; ++r)
@@ -208,16 +215,24 @@ std::string build_host_plan(int dim, int n, double half_width, int ntilde, int f
         if (hp.jobs[jb].pp >= 0) hp.dir_job[hp.jobs[jb].pp] = (int32_t)jb;
     }
 
-    // Dirichlet table D_M(s) = sum_{|m|<=M} cos(2 pi m s / n), M = 0..Nt, built
-    // in FP64 with the phase m*s reduced mod n in integers.
+    // Multiplier rows, M = 0..Nt, built in FP64 with the phase m*s reduced mod n
+    // in integers: first the Dirichlet kernel D_M(s) = sum_{|m|<=M} cos(2 pi m s / n)
+    // (the 2D plane sum), then the line multipliers
+    // A_M(s) = sum_{0<|m|<=M} rho(m) cos(2 pi m s / n), rho = 1 (uniform profile,
+    // A_M = D_M - 1) or 1/|m| (delta profile).
     std::vector<double> ct(n);
     for (int r = 0; r < n; ++r) ct[r] = std::cos(2.0 * M_PI * r / n);
-    hp.dirichlet.assign((size_t)(ntilde + 1) * n, 0.f);
+    const size_t rows = (size_t)(ntilde + 1) * n;
+    hp.dirichlet.assign(2 * rows, 0.f);
     for (int M = 0; M <= ntilde; ++M)
         for (int s = 0; s < n; ++s) {
-            double acc = 1.0;
-            for (int m = 1; m <= M; ++m) acc += 2.0 * ct[(m * s) % n];
-            hp.dirichlet[(size_t)M * n + s] = (float)acc;
+            double d = 1.0, a = 0.0;
+            for (int m = 1; m <= M; ++m) {
+                d += 2.0 * ct[(m * s) % n];
+                a += 2.0 * ct[(m * s) % n] / (line_weight ? (double)m : 1.0);
+            }
+            hp.dirichlet[(size_t)M * n + s] = (float)d;
+            hp.dirichlet[rows + (size_t)M * n + s] = (float)a;
         }
 
     // 3D plane multipliers alpha'_p(K) = sum_{l.e_p = 0, |l|_inf <= Nt} cos(2 pi K.l / n)

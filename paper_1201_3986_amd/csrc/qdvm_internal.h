@@ -27,7 +27,8 @@ struct DevPlan {
     int32_t npts;                // n^dim
     int32_t mode;                // 0: Q(f, f); 1: near-equilibrium Q(f, f) - Q(M, M)
     const JobDesc* jobs;         // [njobs]
-    const float* dirichlet;      // [(ntilde+1) * n]: D_M(s) = sum_{|m|<=M} cos(2 pi m s / n)
+    const float* dirichlet;      // [2 (ntilde+1) n]: rows D_M(s) = sum_{|m|<=M} cos(2 pi m s / n), then the
+                                 // line multipliers A_M(s) = sum_{0<|m|<=M} rho(m) cos(2 pi m s / n)
     const float* aperp;          // 3D: [njobs][npts] plane multipliers, spectral layout; 2D: null
     const float* w_default;      // [P] default weights
     const int32_t* dir_job;      // [P] job holding each direction, -1 if M_p = 0
@@ -53,12 +54,13 @@ struct DevScratch {
 
 struct HostPlan {
     int32_t dim = 0, n = 0, ntilde = 0, P = 0, mode = 0;
+    int32_t line_weight = 0;          // 0: uniform along a line; 1: 1/|m| (delta quadrature)
     double half_width = 0, h = 0;
     std::vector<int32_t> dirs;       // P * dim
     std::vector<double> weights;     // P
     std::vector<int32_t> M;          // P
     std::vector<JobDesc> jobs;
-    std::vector<float> dirichlet;    // (ntilde+1) * n
+    std::vector<float> dirichlet;    // 2 (ntilde+1) n: D_M rows, then A_M rows
     std::vector<float> aperp;        // njobs * npts (3D)
     // device copies
     JobDesc* d_jobs = nullptr;
@@ -95,7 +97,8 @@ struct HostPlan {
 // Host plan construction (no device work).  Returns an empty string on success
 // or a message describing the invalid argument.
 std::string build_host_plan(int dim, int n, double half_width, int ntilde, int farey_order,
-                            int num_dirs, const int32_t* dirs, const double* weights, HostPlan& hp);
+                            int num_dirs, const int32_t* dirs, const double* weights, int line_weight,
+                            HostPlan& hp);
 
 bool supported_size(int dim, int n);
 

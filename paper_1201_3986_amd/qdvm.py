@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "_build", "libqdvm.so")
 
 QDVM_OK, QDVM_EINVAL, QDVM_EUNSUPPORTED, QDVM_ENOMEM, QDVM_EDEVICE = 0, -1, -2, -3, -4
 MODE_FULL, MODE_NEAR_EQUILIBRIUM = 0, 1
-ABI_VERSION = 3
+LINE_UNIFORM, LINE_DELTA = 0, 1
+_LINE_WEIGHTS = {"uniform": LINE_UNIFORM, "delta": LINE_DELTA}
+ABI_VERSION = 4
 _MODES = {"full": MODE_FULL, "near_equilibrium": MODE_NEAR_EQUILIBRIUM}
 
 _lock = threading.Lock()
@@ -35,13 +37,13 @@ class Desc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("half_width", ctypes.c_double),
                 ("ntilde", ctypes.c_int32), ("farey_order", ctypes.c_int32), ("num_dirs", ctypes.c_int32),
                 ("dirs", ctypes.POINTER(ctypes.c_int32)), ("weights", ctypes.POINTER(ctypes.c_double)),
-                ("mode", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("line_weight", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("ntilde", ctypes.c_int32),
                 ("num_dirs", ctypes.c_int32), ("num_jobs", ctypes.c_int32), ("h", ctypes.c_double),
-                ("mode", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("line_weight", ctypes.c_int32)]
 
 
 def load():
@@ -112,9 +114,18 @@ def _mode(mode):
     return int(mode)
 
 
-def _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights, mode=MODE_FULL):
+def _line_weight(lw):
+    if isinstance(lw, str):
+        if lw not in _LINE_WEIGHTS:
+            raise ValueError("line_weight must be one of %s" % sorted(_LINE_WEIGHTS))
+        return _LINE_WEIGHTS[lw]
+    return int(lw)
+
+
+def _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights, mode=MODE_FULL, line_weight=LINE_UNIFORM):
     keep = []
-    d = Desc(dim, n, float(half_width), ntilde, farey_order, num_dirs, None, None, _mode(mode))
+    d = Desc(dim, n, float(half_width), ntilde, farey_order, num_dirs, None, None, _mode(mode),
+             _line_weight(line_weight))
     if dirs is not None:
         a = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1, dim))
         keep.append(a)
@@ -127,10 +138,11 @@ def _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights, mode
     return d, keep
 
 
-def describe(dim, n, half_width=8.0, ntilde=0, farey_order=0, num_dirs=0, dirs=None, weights=None):
+def describe(dim, n, half_width=8.0, ntilde=0, farey_order=0, num_dirs=0, dirs=None, weights=None,
+             line_weight=LINE_UNIFORM):
     """Host-only: (dirs, weights, line lengths) a descriptor selects."""
     lib = load()
-    d, keep = _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights)
+    d, keep = _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights, line_weight=line_weight)
     P = ctypes.c_int32(0)
     _check(lib.qdvm_describe(ctypes.byref(d), ctypes.byref(P), None, None, None, 0))
     dirs_out = np.zeros((P.value, dim), dtype=np.int32)
@@ -157,11 +169,13 @@ class Plan:
     """An immutable plan (directions, weights, multiplier tables) on the current device."""
 
     def __init__(self, dim, n, half_width=8.0, ntilde=0, farey_order=0, num_dirs=0, dirs=None, weights=None,
-                 mode=MODE_FULL):
+                 mode=MODE_FULL, line_weight=LINE_UNIFORM):
         """mode: "full" (Q(f, f)) or "near_equilibrium" (Q(f, f) - Q(M, M) with M
-        the cell's Maxwellian, evaluated as Q(g, f) + Q(M, g), g = f - M)."""
+        the cell's Maxwellian, evaluated as Q(g, f) + Q(M, g), g = f - M).
+        line_weight: "uniform" (a(m e_p) = w_p, the paper's lattice weights) or
+        "delta" (a(m e_p) = w_p / |m|, the quadrature of delta(x . y))."""
         lib = load()
-        d, keep = _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights, mode)
+        d, keep = _desc(dim, n, half_width, ntilde, farey_order, num_dirs, dirs, weights, mode, line_weight)
         h = ctypes.c_void_p()
         _check(lib.qdvm_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -169,6 +183,7 @@ class Plan:
         self.request = dict(half_width=float(half_width), ntilde=int(ntilde), farey_order=int(farey_order),
                             num_dirs=int(num_dirs), explicit_dirs=dirs is not None,
                             explicit_weights=weights is not None)
+        self.line_weight = _line_weight(line_weight)
         info = PlanInfo()
         _check(lib.qdvm_plan_info(h, ctypes.byref(info)))
         self.dim, self.n, self.ntilde = info.dim, info.n, info.ntilde

@@ -23,9 +23,13 @@ Workloads (random draws in the order listed, numpy default_rng(seed)):
 * ``c5`` (seed 105): 64 cells 3D n = 32, R = 8, each drawn from the c3 family;
   cotangent ~ N(0, 1) per point.
 
+* ``bkw`` (no randomness): the BKW solution of the 2D Maxwell gas (Sec. 4)
+  sampled on the grid at time t, the accuracy study's initial data and exact
+  reference.
+
 The paper gives no public dataset; its only workload is the analytic BKW
-solution of the 2D Maxwell gas (Sec. 4).  These families stand in for it with
-the same grids and box sizes.
+solution of the 2D Maxwell gas (Sec. 4).  The random families stand in for it
+with the same grids and box sizes.
 """
 from __future__ import annotations
 
@@ -173,3 +177,14 @@ def relaxation_mix(seed: int, cells: int, d: int, n: int, R: float = 8.0) -> tup
                        + maxwellian(d, n, R, 1.0, -u, rng.uniform(0.5, 1.5)))
         kind.append(k)
     return np.stack(out).astype(np.float32), np.array(kind, dtype=np.int32)
+
+
+def bkw(n: int, R: float, t: float) -> np.ndarray:
+    """The BKW solution of the space-homogeneous 2D Maxwell gas (Sec. 4),
+    f(t, v) = exp(-|v|^2 / 2S) / (2 pi S^2) (2S - 1 + (1 - S) |v|^2 / (2S)),
+    S = 1 - exp(-t/8) / 2, sampled on the n x n grid of [-R, R)^2 (float64).
+    Unit mass, zero mean velocity, unit temperature per degree of freedom."""
+    vx, vy = velocity_axes(2, n, R)
+    v2 = vx * vx + vy * vy
+    S = 1.0 - np.exp(-t / 8.0) / 2.0
+    return np.exp(-v2 / (2.0 * S)) / (2.0 * np.pi * S * S) * (2.0 * S - 1.0 + (1.0 - S) / (2.0 * S) * v2)

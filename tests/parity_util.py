@@ -22,7 +22,7 @@ def assert_oracle_direction_set(plan):
         assert np.array_equal(np.asarray(plan.dirs), ref), "plan directions differ from the oracle's"
     if not r["explicit_weights"]:
         h = 2.0 * r["half_width"] / plan.n
-        ref_w = oracle.default_weights(plan.dim, h, plan.dirs)
+        ref_w = oracle.default_weights(plan.dim, h, plan.dirs, getattr(plan, "line_weight", 0))
         assert np.allclose(plan.weights, ref_w, rtol=1e-14, atol=0.0), "plan weights differ from the oracle's"
 
 
@@ -31,7 +31,7 @@ def oracle_q(plan, f32, w=None):
     assert_oracle_direction_set(plan)
     weights = np.float32(plan.weights if w is None else w).astype(np.float64)
     f64 = np.asarray(f32, dtype=np.float32).astype(np.float64)
-    return oracle.collide(plan.dim, plan.n, plan.ntilde, plan.dirs, weights, f64)
+    return oracle.collide(plan.dim, plan.n, plan.ntilde, plan.dirs, weights, f64, getattr(plan, "line_weight", 0))
 
 
 def oracle_vjp(plan, f32, c32, w=None):
@@ -39,7 +39,7 @@ def oracle_vjp(plan, f32, c32, w=None):
     weights = np.float32(plan.weights if w is None else w).astype(np.float64)
     return oracle.vjp(plan.dim, plan.n, plan.ntilde, plan.dirs, weights,
                       np.asarray(f32, np.float32).astype(np.float64),
-                      np.asarray(c32, np.float32).astype(np.float64))
+                      np.asarray(c32, np.float32).astype(np.float64), getattr(plan, "line_weight", 0))
 
 
 def oracle_grad_w(plan, f32, c32):
@@ -51,7 +51,7 @@ def oracle_grad_w(plan, f32, c32):
     c = np.asarray(c32, np.float32).astype(np.float64).reshape(-1, plan.npts)
     gw = np.zeros(plan.num_dirs)
     for k in range(f.shape[0]):
-        terms = oracle.collide_terms(plan.dim, plan.n, plan.ntilde, plan.dirs, f[k])
+        terms = oracle.collide_terms(plan.dim, plan.n, plan.ntilde, plan.dirs, f[k], getattr(plan, "line_weight", 0))
         gw += terms @ c[k]
     return gw
 

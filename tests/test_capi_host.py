@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
     assert len(names) >= 12
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.qdvm_abi_version() == qdvm.ABI_VERSION == 3
+    assert lib.qdvm_abi_version() == qdvm.ABI_VERSION == 4
 
 
 def test_status_strings():
@@ -96,3 +96,20 @@ def test_null_arguments_rejected():
     assert lib.qdvm_vjp(None, 1, None, None, None, None, None, None) == qdvm.QDVM_EINVAL
     assert lib.qdvm_plan_destroy(None) == qdvm.QDVM_OK
     assert b"null" in lib.qdvm_last_error() or lib.qdvm_last_error() == b""
+
+
+def test_delta_line_weight_defaults_and_validation():
+    # the delta profile's default weight is h^(2d-2) on every line (a(k) =
+    # h^(2d-2)/gcd(k) after the 1/|m| along the line), as the oracle's
+    for d, n in ((2, 32), (3, 24)):
+        h = 2 * 8.0 / n
+        dirs, w, M = qdvm.describe(d, n, 8.0, num_dirs=13, line_weight="delta")
+        assert np.array_equal(dirs, oracle.first_lines(d, 13))
+        assert np.allclose(w, oracle.default_weights(d, h, dirs, line_weight=1), rtol=1e-15, atol=0)
+        assert np.allclose(w, h ** (2 * d - 2), rtol=1e-15, atol=0)
+    lib = qdvm.load()
+    d, keep = qdvm._desc(2, 16, 8.0, 0, 0, 4, None, None, 0, 0)
+    d.line_weight = 2
+    P = ctypes.c_int32(0)
+    assert lib.qdvm_describe(ctypes.byref(d), ctypes.byref(P), None, None, None, 0) == qdvm.QDVM_EINVAL
+    assert b"line_weight" in lib.qdvm_last_error()

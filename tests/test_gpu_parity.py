@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1201_3986_amd import workloads
+import oracle
 from parity_util import loss_total, oracle_q, per_cell_rel_linf, rel_linf
 
 pytestmark = pytest.mark.gpu
@@ -397,3 +398,31 @@ def test_eval_and_vjp_captured_in_graph(gpu_lib, d, n, P, batch):
     sel = [0, batch - 1]
     assert per_cell_rel_linf(q_ref.reshape(batch, -1)[sel], oracle_q(plan, f[sel]), n ** d).max() <= TOL
     del g
+
+
+@pytest.mark.parametrize("d,n,P,batch", [(2, 16, 8, 5), (2, 64, 16, 3), (2, 32, 13, 4), (3, 24, 16, 2), (3, 32, 8, 1)])
+def test_delta_line_weight_profile(gpu_lib, d, n, P, batch):
+    # the delta profile (a(m e_p) = w_p / |m|, default w_p = h^(2d-2)): no 2D
+    # pairing, weighted line multipliers; evaluation, adjoint and the bilinear
+    # operator against the oracle with the same profile
+    import torch
+    from parity_util import oracle_vjp
+    f = workloads.random_positive(2500 + n + P, d, n, batch)
+    g = workloads.random_positive(2600 + n + P, d, n, batch)
+    c = np.random.default_rng(2601).standard_normal(f.shape).astype(np.float32)
+    plan = gpu_lib.Plan(d, n, 8.0, num_dirs=P, line_weight="delta")
+    assert plan.line_weight == 1 and plan.num_jobs == P
+    q = _eval(plan, f)
+    eq = per_cell_rel_linf(q, oracle_q(plan, f), n ** d).max()
+    gf, gw = plan.vjp(_dev(f), _dev(c))
+    qb = plan.eval_bilinear(_dev(g), _dev(f))
+    torch.cuda.synchronize()
+    rf, rw = oracle_vjp(plan, f, c)
+    w64 = np.float32(plan.weights).astype(np.float64)
+    rb = oracle.collide_bilinear(d, n, plan.ntilde, plan.dirs, w64, g.astype(np.float64), f.astype(np.float64),
+                                 line_weight=1)
+    ef = per_cell_rel_linf(gf.cpu().numpy(), rf, n ** d).max()
+    ew = rel_linf(gw.cpu().numpy(), rw)
+    eb = per_cell_rel_linf(qb.cpu().numpy(), rb, n ** d).max()
+    print("delta profile d=%d n=%d P=%d: eval %.2e vjp %.2e / %.2e bilinear %.2e" % (d, n, P, eq, ef, ew, eb))
+    assert max(eq, ef, ew, eb) <= TOL
