@@ -315,12 +315,43 @@ qdvm_status qdvm_adaptive_eval(qdvm_adaptive_t adaptive, const float* f, float* 
                                float* dist, hipStream_t stream);
 qdvm_status qdvm_adaptive_destroy(qdvm_adaptive_t adaptive);   /* synchronises the device first; NULL is a no-op */
 
-/* Kernel variant (FFT radix order) used by eval (op 0) and vjp (op 1):
- * -1 restores the built-in default (4 x 8 pencils for 3D n = 32, else
- * variant 0).  qdvm_autotune times every variant on
- * `batch` synthetic cells on `stream` and keeps the fastest per op. */
+/*
+ * Launch shape of the evaluation (op 0: qdvm_eval, qdvm_eval_bilinear,
+ * qdvm_eval_noalloc) and of the adjoint (op 1: qdvm_vjp) of a plan.  Every
+ * shape computes the same operator; they differ in speed and, by summation
+ * order, in the last bits.
+ */
+typedef struct {
+    int32_t radix;      /* FFT radix order of the pencil transforms, 0 or 1; -1: the built-in default
+                           (4 x 8 for 3D n = 32, else 0) */
+    int32_t threads;    /* 3D n = 16 and 32: 0 one pencil per lane (256 / 1024 threads per cell),
+                           1 two pencils per lane (128 / 512 threads); else 0 */
+    int32_t split;      /* 3D: direction split of small batches, 0 automatic (when the batch leaves
+                           more than half of the workgroup slots idle), 1 never, G = 2..8 that many
+                           workgroups per cell whenever they fit; 2D: 0 or 1 */
+    int32_t grid_div;   /* 1, 2 or 4: persistent workgroups = occupancy x CUs / grid_div */
+} qdvm_launch_config;
+
+/* Set (cfg NULL: restore the defaults) or read the launch shape of op 0 or 1.
+ * EINVAL for a field out of range.  The plan's workspace covers every shape. */
+qdvm_status qdvm_set_config(qdvm_plan_t plan, int32_t op, const qdvm_launch_config* cfg);
+qdvm_status qdvm_get_config(qdvm_plan_t plan, int32_t op, qdvm_launch_config* cfg);
+
+/* Radix order alone (the `radix` field above): -1 restores the default. */
 qdvm_status qdvm_set_variant(qdvm_plan_t plan, int32_t op, int32_t variant);
 qdvm_status qdvm_get_variant(qdvm_plan_t plan, int32_t op, int32_t* variant);
+
+/*
+ * Autotuner: times every distinct launch of the shape space above (radix x
+ * threads x grid_div x split) for evaluation and adjoint on `batch` synthetic
+ * cells on `stream` and keeps the fastest per op.  If the environment
+ * variable QDVM_TUNE_CACHE names a file, shapes are looked up there first,
+ * keyed by (GPU architecture and CU count, d, n, Nt, P, jobs, mode, line
+ * weight, op, ceil(log2 batch)), and the tuned ones are written back (the file
+ * is replaced through a temporary and a rename; concurrent tuners may lose an
+ * entry, never corrupt the file).  Allocates and frees its synthetic buffers
+ * and synchronises `stream`.
+ */
 qdvm_status qdvm_autotune(qdvm_plan_t plan, int32_t batch, hipStream_t stream);
 
 const char* qdvm_status_string(qdvm_status status);

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <unistd.h>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,7 +21,9 @@
 
 struct qdvm_plan_s {
     qdvm::HostPlan hp;
-    int variant[2] = {-1, -1};
+    // launch shape per operation: 0 evaluation (also the bilinear and
+    // allocation-free calls), 1 adjoint; radix -1 = the built-in default
+    qdvm_launch_config cfg[2] = {{-1, 0, 0, 1}, {-1, 0, 0, 1}};
     std::mutex mu;
 };
 
@@ -188,14 +192,17 @@ qdvm_status workspace_bound(const qdvm::HostPlan& hp, size_t& bytes)
 {
     const qdvm::DevPlan pl = hp.dev();
     bytes = 0;
+    const int nthreads = qdvm::has_alt_threads(hp.dim, hp.n) ? 2 : 1;
     for (int op = 0; op < 3; ++op)
-        for (int v = 0; v < qdvm::num_variants(hp.dim, hp.n); ++v) {
-            const int slots = qdvm::max_slots(pl, op, v);
-            if (slots <= 0) return fail(QDVM_EDEVICE, "could not size the plan workspace (occupancy query failed)");
-            const WsLayout L = ws_layout(hp, (size_t)slots, (size_t)slots,
-                                         (hp.dim == 3 && op != 2) ? (size_t)slots : 0, op);
-            bytes = std::max(bytes, L.total);
-        }
+        for (int v = 0; v < qdvm::num_variants(hp.dim, hp.n); ++v)
+            for (int t = 0; t < nthreads; ++t) {
+                const int slots = qdvm::max_slots(pl, op, v, t);
+                if (slots <= 0)
+                    return fail(QDVM_EDEVICE, "could not size the plan workspace (occupancy query failed)");
+                const WsLayout L = ws_layout(hp, (size_t)slots, (size_t)slots,
+                                             (hp.dim == 3 && op != 2) ? (size_t)slots : 0, op);
+                bytes = std::max(bytes, L.total);
+            }
     return QDVM_OK;
 }
 
@@ -216,17 +223,42 @@ qdvm::DevScratch scratch_of(void* base, const qdvm::HostPlan& hp, const WsLayout
     return s;
 }
 
-int effective_variant(const qdvm_plan_s* p, int op)
+// Kernel variant (radix order) and launch shape of an operation.
+struct Shape {
+    int variant;
+    qdvm::LaunchLimits lim;
+};
+
+Shape shape_of(const qdvm::HostPlan& hp, const qdvm_launch_config& c)
 {
-    return p->variant[op] >= 0 ? p->variant[op] : qdvm::default_variant(p->hp.dim, p->hp.n);
+    Shape sh;
+    sh.variant = c.radix >= 0 ? c.radix : qdvm::default_variant(hp.dim, hp.n);
+    sh.lim.threads = c.threads;
+    sh.lim.split = c.split;
+    sh.lim.grid_div = c.grid_div;
+    return sh;
+}
+
+Shape effective_shape(const qdvm_plan_s* p, int op) { return shape_of(p->hp, p->cfg[op]); }
+
+qdvm_status check_config(const qdvm::HostPlan& hp, const qdvm_launch_config& c)
+{
+    if (c.radix < -1 || c.radix >= qdvm::num_variants(hp.dim, hp.n)) return fail(QDVM_EINVAL, "radix out of range");
+    if (c.threads < 0 || c.threads > 1 || (c.threads == 1 && !qdvm::has_alt_threads(hp.dim, hp.n)))
+        return fail(QDVM_EINVAL, "threads must be 0, or 1 where an alternative workgroup size exists (3D n = 16, 32)");
+    if (c.split < 0 || c.split > 8 || (c.split > 1 && hp.dim != 3))
+        return fail(QDVM_EINVAL, "split must be 0 (automatic), 1 (never) or 2..8 (3D only)");
+    if (c.grid_div != 1 && c.grid_div != 2 && c.grid_div != 4) return fail(QDVM_EINVAL, "grid_div must be 1, 2 or 4");
+    return QDVM_OK;
 }
 
 qdvm_status do_eval(qdvm_plan_s* p, int batch, const float* f, float* q, const float* w, float dt,
-                    hipStream_t st, int variant)
+                    hipStream_t st, const Shape& sh)
 {
     qdvm::HostPlan& hp = p->hp;
     const qdvm::DevPlan pl = hp.dev();
-    qdvm::LaunchInfo li = qdvm::eval_launch_info(pl, batch, variant);
+    const int variant = sh.variant;
+    qdvm::LaunchInfo li = qdvm::eval_launch_info(pl, batch, variant, sh.lim);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
     const WsLayout L = call_layout(hp, li, batch, WS_EVAL);
     if (L.total > hp.ws_bytes) return fail(QDVM_EDEVICE, "internal: launch needs more than the plan workspace");
@@ -245,11 +277,12 @@ qdvm_status do_eval(qdvm_plan_s* p, int batch, const float* f, float* q, const f
 }
 
 qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, const float* w, float* gf,
-                   float* gw, hipStream_t st, int variant)
+                   float* gw, hipStream_t st, const Shape& sh)
 {
     qdvm::HostPlan& hp = p->hp;
     const qdvm::DevPlan pl = hp.dev();
-    qdvm::LaunchInfo li = qdvm::vjp_launch_info(pl, batch, variant);
+    const int variant = sh.variant;
+    qdvm::LaunchInfo li = qdvm::vjp_launch_info(pl, batch, variant, sh.lim);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the adjoint kernel");
     const WsLayout L = call_layout(hp, li, batch, WS_ADJOINT);
     if (L.total > hp.ws_bytes) return fail(QDVM_EDEVICE, "internal: launch needs more than the plan workspace");
@@ -269,11 +302,12 @@ qdvm_status do_vjp(qdvm_plan_s* p, int batch, const float* f, const float* c, co
 
 
 qdvm_status do_eval_bilinear(qdvm_plan_s* p, int batch, const float* g, const float* f, float* q, const float* w,
-                             float dt, hipStream_t st, int variant)
+                             float dt, hipStream_t st, const Shape& sh)
 {
     qdvm::HostPlan& hp = p->hp;
     const qdvm::DevPlan pl = hp.dev();
-    qdvm::LaunchInfo li = qdvm::bilinear_launch_info(pl, batch, variant);
+    const int variant = sh.variant;
+    qdvm::LaunchInfo li = qdvm::bilinear_launch_info(pl, batch, variant, sh.lim);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the bilinear kernel");
     const WsLayout L = call_layout(hp, li, batch, WS_BILINEAR);
     if (L.total > hp.ws_bytes) return fail(QDVM_EDEVICE, "internal: launch needs more than the plan workspace");
@@ -296,11 +330,12 @@ qdvm_status do_eval_bilinear(qdvm_plan_s* p, int batch, const float* g, const fl
 // resident slots of the natural launch do not fit, fewer workgroups, each
 // persistent over more cells.
 qdvm_status eval_in(qdvm_plan_s* p, int batch, const float* f, float* q, const float* w, float dt, hipStream_t st,
-                    int variant, void* ws, size_t ws_bytes)
+                    const Shape& sh, void* ws, size_t ws_bytes)
 {
     qdvm::HostPlan& hp = p->hp;
     const qdvm::DevPlan pl = hp.dev();
-    qdvm::LaunchLimits lim;
+    const int variant = sh.variant;
+    qdvm::LaunchLimits lim = sh.lim;
     lim.allow_split = false;
     qdvm::LaunchInfo li = qdvm::eval_launch_info(pl, batch, variant, lim);
     if (li.grid <= 0) return fail(QDVM_EDEVICE, "could not configure the evaluation kernel");
@@ -534,7 +569,7 @@ qdvm_status qdvm_eval(qdvm_plan_t p, int32_t batch, const float* f, float* q, co
     std::lock_guard<std::mutex> lock(p->mu);
     qdvm_status s = check_device(p);
     if (s != QDVM_OK) return s;
-    return do_eval(p, batch, f, q, w, dt, stream, effective_variant(p, 0));
+    return do_eval(p, batch, f, q, w, dt, stream, effective_shape(p, 0));
 }
 
 }  // extern "C"
@@ -552,7 +587,7 @@ qdvm_status eval_with_scratch(qdvm_plan_t p, int32_t batch, const float* f, floa
     std::lock_guard<std::mutex> lock(p->mu);
     qdvm_status s = check_device(p);
     if (s != QDVM_OK) return s;
-    return eval_in(p, batch, f, q, w, dt, stream, effective_variant(p, 0), ws, ws_bytes);
+    return eval_in(p, batch, f, q, w, dt, stream, effective_shape(p, 0), ws, ws_bytes);
 }
 
 qdvm_status record_error(qdvm_status st, const char* msg) { return fail(st, msg); }
@@ -572,7 +607,7 @@ qdvm_status qdvm_eval_bilinear(qdvm_plan_t p, int32_t batch, const float* g, con
     std::lock_guard<std::mutex> lock(p->mu);
     qdvm_status s = check_device(p);
     if (s != QDVM_OK) return s;
-    return do_eval_bilinear(p, batch, g, f, q, w, dt, stream, effective_variant(p, 0));
+    return do_eval_bilinear(p, batch, g, f, q, w, dt, stream, effective_shape(p, 0));
 }
 
 qdvm_status qdvm_vjp(qdvm_plan_t p, int32_t batch, const float* f, const float* cot, const float* w,
@@ -586,7 +621,7 @@ qdvm_status qdvm_vjp(qdvm_plan_t p, int32_t batch, const float* f, const float* 
     std::lock_guard<std::mutex> lock(p->mu);
     qdvm_status s = check_device(p);
     if (s != QDVM_OK) return s;
-    return do_vjp(p, batch, f, cot, w, grad_f, grad_w, stream, effective_variant(p, 1));
+    return do_vjp(p, batch, f, cot, w, grad_f, grad_w, stream, effective_shape(p, 1));
 }
 
 qdvm_status qdvm_set_variant(qdvm_plan_t p, int32_t op, int32_t variant)
@@ -596,7 +631,7 @@ qdvm_status qdvm_set_variant(qdvm_plan_t p, int32_t op, int32_t variant)
     if (variant < -1 || variant >= qdvm::num_variants(p->hp.dim, p->hp.n))
         return fail(QDVM_EINVAL, "variant out of range");
     std::lock_guard<std::mutex> lock(p->mu);
-    p->variant[op] = variant;
+    p->cfg[op].radix = variant;
     return QDVM_OK;
 }
 
@@ -604,9 +639,106 @@ qdvm_status qdvm_get_variant(qdvm_plan_t p, int32_t op, int32_t* variant)
 {
     if (!p || !variant) return fail(QDVM_EINVAL, "null plan or output");
     if (op < 0 || op > 1) return fail(QDVM_EINVAL, "op must be 0 (eval) or 1 (vjp)");
-    *variant = effective_variant(p, op);
+    *variant = effective_shape(p, op).variant;
     return QDVM_OK;
 }
+
+qdvm_status qdvm_set_config(qdvm_plan_t p, int32_t op, const qdvm_launch_config* cfg)
+{
+    if (!p) return fail(QDVM_EINVAL, "null plan");
+    if (op < 0 || op > 1) return fail(QDVM_EINVAL, "op must be 0 (eval) or 1 (vjp)");
+    const qdvm_launch_config def = {-1, 0, 0, 1};
+    const qdvm_launch_config c = cfg ? *cfg : def;
+    const qdvm_status s = check_config(p->hp, c);
+    if (s != QDVM_OK) return s;
+    std::lock_guard<std::mutex> lock(p->mu);
+    p->cfg[op] = c;
+    return QDVM_OK;
+}
+
+qdvm_status qdvm_get_config(qdvm_plan_t p, int32_t op, qdvm_launch_config* cfg)
+{
+    if (!p || !cfg) return fail(QDVM_EINVAL, "null plan or output");
+    if (op < 0 || op > 1) return fail(QDVM_EINVAL, "op must be 0 (eval) or 1 (vjp)");
+    std::lock_guard<std::mutex> lock(p->mu);
+    *cfg = p->cfg[op];
+    if (cfg->radix < 0) cfg->radix = qdvm::default_variant(p->hp.dim, p->hp.n);
+    return QDVM_OK;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- tuning cache
+// One line per tuned (device, plan shape, operation, batch class):
+//   <key> <radix> <threads> <split> <grid_div> <ms>
+// key = qdvm4:<arch>:<cus>:<d>:<n>:<Nt>:<P>:<jobs>:<mode>:<line_weight>:<op>:<ceil log2 batch>.
+
+std::string tune_key(const qdvm::HostPlan& hp, int op, int batch)
+{
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, hp.device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    for (char& ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    int bclass = 0;
+    while ((1 << bclass) < batch && bclass < 30) ++bclass;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "qdvm4:%s:%d:%d:%d:%d:%d:%d:%d:%d:%d:%d", arch.c_str(), cus, hp.dim, hp.n,
+                  hp.ntilde, hp.P, (int)hp.jobs.size(), hp.mode, hp.line_weight, op, bclass);
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, qdvm_launch_config& out)
+{
+    FILE* fh = std::fopen(path, "r");
+    if (!fh) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, fh)) {
+        char k[300];
+        qdvm_launch_config c{};
+        float ms = 0.f;
+        if (std::sscanf(line, "%299s %d %d %d %d %f", k, &c.radix, &c.threads, &c.split, &c.grid_div, &ms) == 6 &&
+            key == k) {
+            out = c;
+            found = true;   // the last entry of a key wins
+        }
+    }
+    std::fclose(fh);
+    return found;
+}
+
+// Replaces or appends the entry of `key`; the file is rewritten through a
+// temporary and renamed, so a concurrent reader never sees a partial file.
+void cache_store(const char* path, const std::string& key, const qdvm_launch_config& c, float ms)
+{
+    std::vector<std::string> lines;
+    if (FILE* fh = std::fopen(path, "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof line, fh)) {
+            char k[300];
+            if (std::sscanf(line, "%299s", k) == 1 && key == k) continue;
+            lines.push_back(line);
+        }
+        std::fclose(fh);
+    }
+    char entry[512];
+    std::snprintf(entry, sizeof entry, "%s %d %d %d %d %.5f\n", key.c_str(), c.radix, c.threads, c.split, c.grid_div,
+                  ms);
+    lines.push_back(entry);
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)::getpid());
+    FILE* out = std::fopen(tmp.c_str(), "w");
+    if (!out) return;
+    for (const auto& l : lines) std::fputs(l.c_str(), out);
+    std::fclose(out);
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
 
 qdvm_status qdvm_autotune(qdvm_plan_t p, int32_t batch, hipStream_t st)
 {
@@ -615,7 +747,18 @@ qdvm_status qdvm_autotune(qdvm_plan_t p, int32_t batch, hipStream_t st)
     std::lock_guard<std::mutex> lock(p->mu);
     qdvm_status s = check_device(p);
     if (s != QDVM_OK) return s;
-    const size_t n = (size_t)batch * p->hp.npts();
+    qdvm::HostPlan& hp = p->hp;
+    const char* cache = std::getenv("QDVM_TUNE_CACHE");
+    if (cache && *cache) {
+        qdvm_launch_config c0{}, c1{};
+        if (cache_lookup(cache, tune_key(hp, 0, batch), c0) && cache_lookup(cache, tune_key(hp, 1, batch), c1) &&
+            check_config(hp, c0) == QDVM_OK && check_config(hp, c1) == QDVM_OK) {
+            p->cfg[0] = c0;
+            p->cfg[1] = c1;
+            return QDVM_OK;
+        }
+    }
+    const size_t n = (size_t)batch * hp.npts();
     float *f = nullptr, *q = nullptr, *g = nullptr;
     hipError_t e = hipMalloc(&f, sizeof(float) * n);
     if (e == hipSuccess) e = hipMalloc(&q, sizeof(float) * n);
@@ -625,27 +768,46 @@ qdvm_status qdvm_autotune(qdvm_plan_t p, int32_t batch, hipStream_t st)
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    const int nv = qdvm::num_variants(p->hp.dim, p->hp.n);
+    const qdvm::DevPlan pl = hp.dev();
+    const int nv = qdvm::num_variants(hp.dim, hp.n);
+    const int nthreads = qdvm::has_alt_threads(hp.dim, hp.n) ? 2 : 1;
+    const int splits3[] = {0, 1, 2, 4, 8};
     for (int op = 0; op < 2 && e == hipSuccess && s == QDVM_OK; ++op) {
         float best = 1e30f;
-        int best_v = 0;
-        for (int v = 0; v < nv && e == hipSuccess && s == QDVM_OK; ++v) {
-            float ms = 0.f;
-            for (int rep = 0; rep < 4 && s == QDVM_OK; ++rep) {
-                if (rep == 1) e = hipEventRecord(a, st);
-                s = op == 0 ? do_eval(p, batch, f, q, nullptr, 0.f, st, v)
-                            : do_vjp(p, batch, f, g, nullptr, q, nullptr, st, v);
-            }
-            if (s != QDVM_OK || e != hipSuccess) break;
-            e = hipEventRecord(b, st);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (e == hipSuccess && ms < best) {
-                best = ms;
-                best_v = v;
-            }
+        qdvm_launch_config best_c = {-1, 0, 0, 1};
+        std::vector<std::vector<int>> seen;   // launches already timed: (variant, grid, block, jsplit)
+        const int nsplit = hp.dim == 3 ? 5 : 1;
+        for (int v = 0; v < nv; ++v)
+            for (int t = 0; t < nthreads; ++t)
+                for (int gd : {1, 2})
+                    for (int si = 0; si < nsplit && e == hipSuccess && s == QDVM_OK; ++si) {
+                        const qdvm_launch_config c = {v, t, splits3[si], gd};
+                        const Shape sh = shape_of(hp, c);
+                        const qdvm::LaunchInfo li = op == 0 ? qdvm::eval_launch_info(pl, batch, v, sh.lim)
+                                                            : qdvm::vjp_launch_info(pl, batch, v, sh.lim);
+                        if (li.grid <= 0) continue;
+                        const std::vector<int> sig = {v, li.grid, li.block, li.jsplit};
+                        if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+                        seen.push_back(sig);
+                        float ms = 0.f;
+                        for (int rep = 0; rep < 4 && s == QDVM_OK; ++rep) {
+                            if (rep == 1) e = hipEventRecord(a, st);
+                            s = op == 0 ? do_eval(p, batch, f, q, nullptr, 0.f, st, sh)
+                                        : do_vjp(p, batch, f, g, nullptr, q, nullptr, st, sh);
+                        }
+                        if (s != QDVM_OK || e != hipSuccess) break;
+                        e = hipEventRecord(b, st);
+                        if (e == hipSuccess) e = hipEventSynchronize(b);
+                        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                        if (e == hipSuccess && ms < best) {
+                            best = ms;
+                            best_c = c;
+                        }
+                    }
+        if (s == QDVM_OK && e == hipSuccess) {
+            p->cfg[op] = best_c;
+            if (cache && *cache) cache_store(cache, tune_key(hp, op, batch), best_c, best / 3.f);
         }
-        p->variant[op] = best_v;
     }
     if (a) hipEventDestroy(a);
     if (b) hipEventDestroy(b);

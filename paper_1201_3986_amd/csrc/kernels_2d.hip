@@ -184,7 +184,7 @@ size_t lds2d(int ntilde) { return sizeof(float) * ((size_t)(256 / N) * N * (N + 
         default: return hipErrorInvalidValue;              \
     }
 
-hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid)
+hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, const LaunchLimits& lim)
 {
     hipError_t e = hipSuccess;
     QDVM_SWITCH_2D(pl.n, {
@@ -194,19 +194,17 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
         if (pl.mode && N == 64) {
             li.block = 128;
             li.lds = sizeof(float) * ((size_t)2 * N * (N + 1) + (size_t)2 * (pl.ntilde + 1) * N);
-            e = variant ? occupancy_grid(k_eval2d_pair<1>, 128, li.lds, batch, li.grid)
-                        : occupancy_grid(k_eval2d_pair<0>, 128, li.lds, batch, li.grid);
-            if (max_grid > 0) li.grid = std::min(li.grid, max_grid);
+            e = variant ? shaped_grid(k_eval2d_pair<1>, 128, li.lds, batch, lim, li.grid)
+                        : shaped_grid(k_eval2d_pair<0>, 128, li.lds, batch, lim, li.grid);
             li.slots = li.grid;
             return e;
         }
         if (pl.mode)
-            e = variant ? occupancy_grid(k_eval2d<N, 1, true>, 256, li.lds, items, li.grid)
-                        : occupancy_grid(k_eval2d<N, 0, true>, 256, li.lds, items, li.grid);
+            e = variant ? shaped_grid(k_eval2d<N, 1, true>, 256, li.lds, items, lim, li.grid)
+                        : shaped_grid(k_eval2d<N, 0, true>, 256, li.lds, items, lim, li.grid);
         else
-            e = variant ? occupancy_grid(k_eval2d<N, 1, false>, 256, li.lds, items, li.grid)
-                        : occupancy_grid(k_eval2d<N, 0, false>, 256, li.lds, items, li.grid);
-        if (max_grid > 0) li.grid = std::min(li.grid, max_grid);
+            e = variant ? shaped_grid(k_eval2d<N, 1, false>, 256, li.lds, items, lim, li.grid)
+                        : shaped_grid(k_eval2d<N, 0, false>, 256, li.lds, items, lim, li.grid);
         li.slots = li.grid * (256 / N);
     });
     return e;
@@ -231,16 +229,15 @@ hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q,
     return hipGetLastError();
 }
 
-hipError_t bil2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid)
+hipError_t bil2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, const LaunchLimits& lim)
 {
     hipError_t e = hipSuccess;
     QDVM_SWITCH_2D(pl.n, {
         li.block = 256;
         li.lds = lds2d<N>(pl.ntilde);
         const int items = (batch + 256 / N - 1) / (256 / N);
-        e = variant ? occupancy_grid(k_eval2d_bil<N, 1>, 256, li.lds, items, li.grid)
-                    : occupancy_grid(k_eval2d_bil<N, 0>, 256, li.lds, items, li.grid);
-        if (max_grid > 0) li.grid = std::min(li.grid, max_grid);
+        e = variant ? shaped_grid(k_eval2d_bil<N, 1>, 256, li.lds, items, lim, li.grid)
+                    : shaped_grid(k_eval2d_bil<N, 0>, 256, li.lds, items, lim, li.grid);
         li.slots = li.grid * (256 / N);
     });
     return e;
@@ -258,16 +255,15 @@ hipError_t launch_bil2d(const DevPlan& pl, int batch, const float* g, const floa
     return hipGetLastError();
 }
 
-hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid)
+hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, const LaunchLimits& lim)
 {
     hipError_t e = hipSuccess;
     QDVM_SWITCH_2D(pl.n, {
         li.block = 256;
         li.lds = lds2d<N>(pl.ntilde);
         const int items = (batch + 256 / N - 1) / (256 / N);
-        e = variant ? occupancy_grid(k_vjp2d<N, 1>, 256, li.lds, items, li.grid)
-                    : occupancy_grid(k_vjp2d<N, 0>, 256, li.lds, items, li.grid);
-        if (max_grid > 0) li.grid = std::min(li.grid, max_grid);
+        e = variant ? shaped_grid(k_vjp2d<N, 1>, 256, li.lds, items, lim, li.grid)
+                    : shaped_grid(k_vjp2d<N, 0>, 256, li.lds, items, lim, li.grid);
         li.slots = li.grid * (256 / N);
     });
     return e;

@@ -26,6 +26,8 @@
 // into the prepared job weights (W_j / n^{2d}) and into Lambda (/ n^d).
 #include "cells_3d.h"
 
+#include <type_traits>
+
 namespace qdvm {
 
 // Gain-accumulator elements per lane kept in LDS by the plain evaluation (the
@@ -323,6 +325,25 @@ constexpr int t3d()
     return N == 32 ? 1024 : (N == 24 ? 576 : (N == 16 ? 256 : 64));
 }
 
+// The alternative workgroup size of a 3D cell (two pencils per lane), a
+// launch shape the autotuner may choose: n = 32 at 512 threads, n = 16 at 128;
+// 0 where there is none.
+template <int N>
+constexpr int t3d_alt()
+{
+    return N == 32 ? 512 : (N == 16 ? 128 : 0);
+}
+
+// Calls f with std::integral_constant<int, T> for the chosen workgroup size.
+template <int N, class F>
+hipError_t with_threads(bool alt, F&& f)
+{
+    if constexpr (t3d_alt<N>() > 0) {
+        if (alt) return f(std::integral_constant<int, t3d_alt<N>()>{});
+    }
+    return f(std::integral_constant<int, t3d<N>()>{});
+}
+
 // transpose buffer | Dirichlet tables | reduction slots (5 doubles per wave) and n Maxwellian
 // factors, or the gain-accumulator elements of the plain evaluation
 template <int N, int T = t3d<N>()>
@@ -335,12 +356,21 @@ size_t lds3d(int ntilde)
     return T == 576 ? std::max<size_t>(bytes, 81 * 1024) : bytes;
 }
 
-// Spread each cell's direction loop over G workgroups when the batch leaves
-// more than half of the workgroup slots (cap) idle.
-void choose_split(const DevPlan& pl, int batch, int cap, LaunchInfo& li)
+// Spread each cell's direction loop over G workgroups.  Automatic (split 0):
+// when the batch leaves more than half of the workgroup slots (cap) idle, G as
+// large as the slots allow (at most 8 and the number of jobs).  split 1: never;
+// split G >= 2: G workgroups per cell whenever batch * G fits in the slots.
+void choose_split(const DevPlan& pl, int batch, int cap, LaunchInfo& li, int split)
 {
-    if (batch < 1 || pl.njobs < 2 || 2 * batch > cap) return;
-    const int G = std::min(std::min(pl.njobs, 8), cap / batch);
+    if (batch < 1 || pl.njobs < 2 || split == 1) return;
+    int G;
+    if (split >= 2) {
+        G = std::min(split, pl.njobs);
+        if ((int64_t)batch * G > cap) return;
+    } else {
+        if (2 * batch > cap) return;
+        G = std::min(std::min(pl.njobs, 8), cap / batch);
+    }
     if (G < 2) return;
     li.jsplit = G;
     li.grid = batch * G;
@@ -358,6 +388,8 @@ void choose_split(const DevPlan& pl, int batch, int cap, LaunchInfo& li)
         default: return hipErrorInvalidValue;              \
     }
 
+bool has_alt_threads(int dim, int n) { return dim == 3 && (n == 16 || n == 32); }
+
 hipError_t launch_prep(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st)
 {
     const int threads = 256;
@@ -371,27 +403,30 @@ LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant, LaunchLim
     LaunchInfo li;
     hipError_t e = hipSuccess;
     if (pl.dim == 2) {
-        e = eval2d_info(pl, batch, variant, li, lim.max_grid);
+        e = eval2d_info(pl, batch, variant, li, lim);
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d<N>();
-                li.block = T;
-                li.lds = lds3d<N>(pl.ntilde);
-                if (pl.mode)
-                    e = variant ? occupancy_grid(k_eval3d<N, T, 1, true>, T, li.lds, batch, li.grid)
-                                : occupancy_grid(k_eval3d<N, T, 0, true>, T, li.lds, batch, li.grid);
-                else
-                    e = variant ? occupancy_grid(k_eval3d<N, T, 1, false>, T, li.lds, batch, li.grid)
-                                : occupancy_grid(k_eval3d<N, T, 0, false>, T, li.lds, batch, li.grid);
-                if (lim.max_grid > 0) li.grid = std::min(li.grid, lim.max_grid);
-                li.slots = li.grid;
-                if (e == hipSuccess && !pl.mode && lim.allow_split) {
-                    int cap = 0;
-                    e = variant ? occupancy_grid(k_eval3d_js<N, T, 1>, T, li.lds, 1 << 30, cap)
-                                : occupancy_grid(k_eval3d_js<N, T, 0>, T, li.lds, 1 << 30, cap);
-                    choose_split(pl, batch, cap, li);
-                }
+                e = with_threads<N>(lim.threads != 0, [&](auto tc) -> hipError_t {
+                    constexpr int T = decltype(tc)::value;
+                    li.block = T;
+                    li.lds = lds3d<N, T>(pl.ntilde);
+                    hipError_t r;
+                    if (pl.mode)
+                        r = variant ? shaped_grid(k_eval3d<N, T, 1, true>, T, li.lds, batch, lim, li.grid)
+                                    : shaped_grid(k_eval3d<N, T, 0, true>, T, li.lds, batch, lim, li.grid);
+                    else
+                        r = variant ? shaped_grid(k_eval3d<N, T, 1, false>, T, li.lds, batch, lim, li.grid)
+                                    : shaped_grid(k_eval3d<N, T, 0, false>, T, li.lds, batch, lim, li.grid);
+                    li.slots = li.grid;
+                    if (r == hipSuccess && !pl.mode && lim.allow_split) {
+                        int cap = 0;
+                        r = variant ? occupancy_grid(k_eval3d_js<N, T, 1>, T, li.lds, 1 << 30, cap)
+                                    : occupancy_grid(k_eval3d_js<N, T, 0>, T, li.lds, 1 << 30, cap);
+                        choose_split(pl, batch, cap, li, lim.split);
+                    }
+                    return r;
+                });
             });
             return e;
         };
@@ -406,23 +441,26 @@ hipError_t launch_eval(const DevPlan& pl, int batch, const float* f, float* q, f
 {
     if (pl.dim == 2) return launch_eval2d(pl, batch, f, q, dt, s, li, variant, st);
     QDVM_SWITCH_3D(pl.n, {
-        constexpr int T = t3d<N>();
-        const dim3 g(li.grid), b(T);
-        if (li.jsplit > 1) {
-            if (variant) hipLaunchKernelGGL((k_eval3d_js<N, T, 1>), g, b, li.lds, st, pl, batch, li.jsplit, f, s);
-            else hipLaunchKernelGGL((k_eval3d_js<N, T, 0>), g, b, li.lds, st, pl, batch, li.jsplit, f, s);
-            const int64_t total = (int64_t)batch * pl.npts;
-            hipLaunchKernelGGL(k_combine, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)), dim3(256), 0,
-                               st, total, li.jsplit, s.part, f, q, dt);
-        } else if (pl.mode) {
-            if (variant) hipLaunchKernelGGL((k_eval3d<N, T, 1, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
-            else hipLaunchKernelGGL((k_eval3d<N, T, 0, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
-        } else {
-            if (variant) hipLaunchKernelGGL((k_eval3d<N, T, 1, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
-            else hipLaunchKernelGGL((k_eval3d<N, T, 0, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
-        }
+        return with_threads<N>(li.block != t3d<N>(), [&](auto tc) -> hipError_t {
+            constexpr int T = decltype(tc)::value;
+            const dim3 g(li.grid), b(T);
+            if (li.jsplit > 1) {
+                if (variant) hipLaunchKernelGGL((k_eval3d_js<N, T, 1>), g, b, li.lds, st, pl, batch, li.jsplit, f, s);
+                else hipLaunchKernelGGL((k_eval3d_js<N, T, 0>), g, b, li.lds, st, pl, batch, li.jsplit, f, s);
+                const int64_t total = (int64_t)batch * pl.npts;
+                hipLaunchKernelGGL(k_combine, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)), dim3(256),
+                                   0, st, total, li.jsplit, s.part, f, q, dt);
+            } else if (pl.mode) {
+                if (variant) hipLaunchKernelGGL((k_eval3d<N, T, 1, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+                else hipLaunchKernelGGL((k_eval3d<N, T, 0, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+            } else {
+                if (variant) hipLaunchKernelGGL((k_eval3d<N, T, 1, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+                else hipLaunchKernelGGL((k_eval3d<N, T, 0, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+            }
+            return hipGetLastError();
+        });
     });
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_prep_bilinear(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st)
@@ -438,17 +476,19 @@ LaunchInfo bilinear_launch_info(const DevPlan& pl, int batch, int variant, Launc
     LaunchInfo li;
     hipError_t e = hipSuccess;
     if (pl.dim == 2) {
-        e = bil2d_info(pl, batch, variant, li, lim.max_grid);
+        e = bil2d_info(pl, batch, variant, li, lim);
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d<N>();
-                li.block = T;
-                li.lds = lds3d<N, T>(pl.ntilde);
-                e = variant ? occupancy_grid(k_eval3d_bil<N, T, 1>, T, li.lds, batch, li.grid)
-                            : occupancy_grid(k_eval3d_bil<N, T, 0>, T, li.lds, batch, li.grid);
-                if (lim.max_grid > 0) li.grid = std::min(li.grid, lim.max_grid);
-                li.slots = li.grid;
+                e = with_threads<N>(lim.threads != 0, [&](auto tc) -> hipError_t {
+                    constexpr int T = decltype(tc)::value;
+                    li.block = T;
+                    li.lds = lds3d<N, T>(pl.ntilde);
+                    hipError_t r = variant ? shaped_grid(k_eval3d_bil<N, T, 1>, T, li.lds, batch, lim, li.grid)
+                                           : shaped_grid(k_eval3d_bil<N, T, 0>, T, li.lds, batch, lim, li.grid);
+                    li.slots = li.grid;
+                    return r;
+                });
             });
             return e;
         };
@@ -463,13 +503,18 @@ hipError_t launch_eval_bilinear(const DevPlan& pl, int batch, const float* g, co
 {
     if (pl.dim == 2) return launch_bil2d(pl, batch, g, f, q, dt, s, li, variant, st);
     QDVM_SWITCH_3D(pl.n, {
-        constexpr int T = t3d<N>();
-        if (variant)
-            hipLaunchKernelGGL((k_eval3d_bil<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, g, f, q, dt, s);
-        else
-            hipLaunchKernelGGL((k_eval3d_bil<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, g, f, q, dt, s);
+        return with_threads<N>(li.block != t3d<N>(), [&](auto tc) -> hipError_t {
+            constexpr int T = decltype(tc)::value;
+            if (variant)
+                hipLaunchKernelGGL((k_eval3d_bil<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, g, f, q, dt,
+                                   s);
+            else
+                hipLaunchKernelGGL((k_eval3d_bil<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, g, f, q, dt,
+                                   s);
+            return hipGetLastError();
+        });
     });
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim)
@@ -477,23 +522,25 @@ LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimi
     LaunchInfo li;
     hipError_t e = hipSuccess;
     if (pl.dim == 2) {
-        e = vjp2d_info(pl, batch, variant, li, lim.max_grid);
+        e = vjp2d_info(pl, batch, variant, li, lim);
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d<N>();
-                li.block = T;
-                li.lds = lds3d<N, T>(pl.ntilde);
-                e = variant ? occupancy_grid(k_vjp3d<N, T, 1>, T, li.lds, batch, li.grid)
-                            : occupancy_grid(k_vjp3d<N, T, 0>, T, li.lds, batch, li.grid);
-                if (lim.max_grid > 0) li.grid = std::min(li.grid, lim.max_grid);
-                li.slots = li.grid;
-                if (e == hipSuccess && lim.allow_split) {
-                    int cap = 0;
-                    e = variant ? occupancy_grid(k_vjp3d_js<N, T, 1>, T, li.lds, 1 << 30, cap)
-                                : occupancy_grid(k_vjp3d_js<N, T, 0>, T, li.lds, 1 << 30, cap);
-                    choose_split(pl, batch, cap, li);
-                }
+                e = with_threads<N>(lim.threads != 0, [&](auto tc) -> hipError_t {
+                    constexpr int T = decltype(tc)::value;
+                    li.block = T;
+                    li.lds = lds3d<N, T>(pl.ntilde);
+                    hipError_t r = variant ? shaped_grid(k_vjp3d<N, T, 1>, T, li.lds, batch, lim, li.grid)
+                                           : shaped_grid(k_vjp3d<N, T, 0>, T, li.lds, batch, lim, li.grid);
+                    li.slots = li.grid;
+                    if (r == hipSuccess && lim.allow_split) {
+                        int cap = 0;
+                        r = variant ? occupancy_grid(k_vjp3d_js<N, T, 1>, T, li.lds, 1 << 30, cap)
+                                    : occupancy_grid(k_vjp3d_js<N, T, 0>, T, li.lds, 1 << 30, cap);
+                        choose_split(pl, batch, cap, li, lim.split);
+                    }
+                    return r;
+                });
             });
             return e;
         };
@@ -503,11 +550,14 @@ LaunchInfo vjp_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimi
     return li;
 }
 
-int max_slots(const DevPlan& pl, int op, int variant)
+int max_slots(const DevPlan& pl, int op, int variant, int threads)
 {
     const int big = 1 << 28;
-    const LaunchInfo li = op == 0 ? eval_launch_info(pl, big, variant)
-                                  : (op == 1 ? vjp_launch_info(pl, big, variant) : bilinear_launch_info(pl, big, variant));
+    LaunchLimits lim;
+    lim.threads = threads;
+    const LaunchInfo li = op == 0 ? eval_launch_info(pl, big, variant, lim)
+                                  : (op == 1 ? vjp_launch_info(pl, big, variant, lim)
+                                             : bilinear_launch_info(pl, big, variant, lim));
     if (li.grid <= 0) return 0;
     int slots = li.slots;
     if (pl.dim == 3 && op != 2 && !(op == 0 && pl.mode)) {
@@ -516,14 +566,15 @@ int max_slots(const DevPlan& pl, int op, int variant)
         hipError_t e = hipSuccess;
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d<N>();
-                const size_t lds = lds3d<N, T>(pl.ntilde);
-                if (op == 0)
-                    e = variant ? occupancy_grid(k_eval3d_js<N, T, 1>, T, lds, 1 << 30, cap)
-                                : occupancy_grid(k_eval3d_js<N, T, 0>, T, lds, 1 << 30, cap);
-                else
-                    e = variant ? occupancy_grid(k_vjp3d_js<N, T, 1>, T, lds, 1 << 30, cap)
-                                : occupancy_grid(k_vjp3d_js<N, T, 0>, T, lds, 1 << 30, cap);
+                e = with_threads<N>(threads != 0, [&](auto tc) -> hipError_t {
+                    constexpr int T = decltype(tc)::value;
+                    const size_t lds = lds3d<N, T>(pl.ntilde);
+                    if (op == 0)
+                        return variant ? occupancy_grid(k_eval3d_js<N, T, 1>, T, lds, 1 << 30, cap)
+                                       : occupancy_grid(k_eval3d_js<N, T, 0>, T, lds, 1 << 30, cap);
+                    return variant ? occupancy_grid(k_vjp3d_js<N, T, 1>, T, lds, 1 << 30, cap)
+                                   : occupancy_grid(k_vjp3d_js<N, T, 0>, T, lds, 1 << 30, cap);
+                });
             });
             return e;
         };
@@ -544,26 +595,29 @@ hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float*
     } else {
         auto body = [&]() -> hipError_t {
             QDVM_SWITCH_3D(pl.n, {
-                constexpr int T = t3d<N>();
-                if (li.jsplit > 1) {
-                    if (variant)
-                        hipLaunchKernelGGL((k_vjp3d_js<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch,
-                                           li.jsplit, f, c, s);
+                return with_threads<N>(li.block != t3d<N>(), [&](auto tc) -> hipError_t {
+                    constexpr int T = decltype(tc)::value;
+                    if (li.jsplit > 1) {
+                        if (variant)
+                            hipLaunchKernelGGL((k_vjp3d_js<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch,
+                                               li.jsplit, f, c, s);
+                        else
+                            hipLaunchKernelGGL((k_vjp3d_js<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch,
+                                               li.jsplit, f, c, s);
+                        const int64_t total = (int64_t)batch * pl.npts;
+                        hipLaunchKernelGGL(k_combine, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)),
+                                           dim3(256), 0, st, total, li.jsplit, s.part, (const float*)nullptr, grad_f,
+                                           0.f);
+                    } else if (variant)
+                        hipLaunchKernelGGL((k_vjp3d<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, c,
+                                           grad_f, s);
                     else
-                        hipLaunchKernelGGL((k_vjp3d_js<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch,
-                                           li.jsplit, f, c, s);
-                    const int64_t total = (int64_t)batch * pl.npts;
-                    hipLaunchKernelGGL(k_combine, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)),
-                                       dim3(256), 0, st, total, li.jsplit, s.part, (const float*)nullptr, grad_f,
-                                       0.f);
-                } else if (variant)
-                    hipLaunchKernelGGL((k_vjp3d<N, T, 1>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, c,
-                                       grad_f, s);
-                else
-                    hipLaunchKernelGGL((k_vjp3d<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, c,
-                                       grad_f, s);
+                        hipLaunchKernelGGL((k_vjp3d<N, T, 0>), dim3(li.grid), dim3(T), li.lds, st, pl, batch, f, c,
+                                           grad_f, s);
+                    return hipGetLastError();
+                });
             });
-            return hipGetLastError();
+            return hipErrorInvalidValue;
         };
         e = body();
     }

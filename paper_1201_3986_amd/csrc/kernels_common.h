@@ -236,4 +236,21 @@ inline hipError_t occupancy_grid(K kernel, int block, size_t lds, int items, int
     return hipSuccess;
 }
 
+// Persistent grid of a kernel: the occupancy grid (capped by the items),
+// divided by grid_div and capped by max_grid.
+template <class K>
+inline hipError_t shaped_grid(K kernel, int block, size_t lds, int items, const LaunchLimits& lim, int& grid)
+{
+    hipError_t e = occupancy_grid(kernel, block, lds, items, grid);
+    if (e != hipSuccess) return e;
+    if (lim.grid_div > 1) {
+        int full = 0;
+        e = occupancy_grid(kernel, block, lds, 1 << 30, full);
+        if (e != hipSuccess) return e;
+        grid = std::min(grid, std::max(1, full / lim.grid_div));
+    }
+    if (lim.max_grid > 0) grid = std::min(grid, lim.max_grid);
+    return hipSuccess;
+}
+
 }  // namespace qdvm

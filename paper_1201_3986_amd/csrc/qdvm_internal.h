@@ -111,13 +111,22 @@ struct LaunchInfo {
     int jsplit = 1;   // > 1: each cell's direction loop is spread over jsplit workgroups
 };
 
-// Launch shape limits: max_grid > 0 caps the number of workgroups (the
-// persistent kernels then take more cells per workgroup); allow_split = false
-// keeps one workgroup per cell even for small 3D batches.
+// Launch shape of a kernel family, chosen by the autotuner or fixed by a
+// caller: max_grid > 0 caps the number of workgroups (the persistent kernels
+// then take more cells per workgroup); grid_div > 1 runs 1/grid_div of the
+// occupancy grid; allow_split = false keeps one workgroup per cell even for
+// small 3D batches, split picks the direction split (0 automatic, 1 never,
+// G >= 2 forced when batch * G workgroups fit); threads = 1 takes the
+// alternative 3D workgroup size (two pencils per lane) where there is one.
 struct LaunchLimits {
     int max_grid = 0;
     bool allow_split = true;
+    int split = 0;
+    int grid_div = 1;
+    int threads = 0;
 };
+// true where a 3D grid size has an alternative workgroup size (n = 16, 32)
+bool has_alt_threads(int dim, int n);
 
 hipError_t launch_prep(const DevPlan& pl, const float* w, DevScratch s, hipStream_t st);
 LaunchInfo eval_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim = LaunchLimits());
@@ -130,23 +139,23 @@ hipError_t launch_prep_bilinear(const DevPlan& pl, const float* w, DevScratch s,
 LaunchInfo bilinear_launch_info(const DevPlan& pl, int batch, int variant, LaunchLimits lim = LaunchLimits());
 hipError_t launch_eval_bilinear(const DevPlan& pl, int batch, const float* g, const float* f, float* q, float dt,
                                 DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
-hipError_t bil2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid);
+hipError_t bil2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, const LaunchLimits& lim);
 hipError_t launch_bil2d(const DevPlan& pl, int batch, const float* g, const float* f, float* q, float dt,
                         DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
 // Largest number of resident cell slots any batch can use with the kernels of
 // op (0: evaluation, 1: adjoint, 2: bilinear evaluation) and variant, direction-split launches
 // included: it bounds the spectral scratch, the grad_w partial rows and the
 // split parts, so a plan's workspace can be sized once for every batch.
-int max_slots(const DevPlan& pl, int op, int variant);
+int max_slots(const DevPlan& pl, int op, int variant, int threads);
 hipError_t launch_vjp(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
                       float* grad_w, const float* w, DevScratch s, const LaunchInfo& li, int variant,
                       hipStream_t st);
 
 // 2D launchers (kernels_2d.hip), called by the dispatch in kernels_3d.hip.
-hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid);
+hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, const LaunchLimits& lim);
 hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q, float dt, DevScratch s,
                          const LaunchInfo& li, int variant, hipStream_t st);
-hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, int max_grid);
+hipError_t vjp2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li, const LaunchLimits& lim);
 hipError_t launch_vjp2d(const DevPlan& pl, int batch, const float* f, const float* c, float* grad_f,
                         DevScratch s, const LaunchInfo& li, int variant, hipStream_t st);
 

@@ -40,6 +40,11 @@ class Desc(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("line_weight", ctypes.c_int32)]
 
 
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("radix", ctypes.c_int32), ("threads", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("grid_div", ctypes.c_int32)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("ntilde", ctypes.c_int32),
                 ("num_dirs", ctypes.c_int32), ("num_jobs", ctypes.c_int32), ("h", ctypes.c_double),
@@ -70,6 +75,8 @@ def load():
             "qdvm_set_variant": [vp, i32, i32],
             "qdvm_get_variant": [vp, i32, i32p],
             "qdvm_autotune": [vp, i32, vp],
+            "qdvm_set_config": [vp, i32, ctypes.POINTER(LaunchConfig)],
+            "qdvm_get_config": [vp, i32, ctypes.POINTER(LaunchConfig)],
             "qdvm_batch_plan": [i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp)],
             "qdvm_batch_destroy": [vp],
             "qdvm_batch_info": [vp, i32p, i32p, dp],
@@ -290,7 +297,19 @@ class Plan:
         return v.value
 
     def autotune(self, batch: int, stream=None):
+        """Time the launch shapes of evaluation and adjoint on `batch` cells and
+        keep the fastest (cached in the file $QDVM_TUNE_CACHE names, if set)."""
         _check(load().qdvm_autotune(self._h, batch, _stream_ptr(stream)))
+
+    def set_config(self, op: int, radix=-1, threads=0, split=0, grid_div=1):
+        """Launch shape of op 0 (evaluation) or 1 (adjoint); no arguments: defaults."""
+        c = LaunchConfig(radix, threads, split, grid_div)
+        _check(load().qdvm_set_config(self._h, op, ctypes.byref(c)))
+
+    def get_config(self, op: int) -> dict:
+        c = LaunchConfig()
+        _check(load().qdvm_get_config(self._h, op, ctypes.byref(c)))
+        return dict(radix=c.radix, threads=c.threads, split=c.split, grid_div=c.grid_div)
 
 
 def _plan_array(plans):
