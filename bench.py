@@ -244,6 +244,39 @@ def adaptive_step(qdvm, workloads, torch, args):
     return out
 
 
+def transform_choice(qdvm, workloads, torch, args):
+    """The transform stage at 2D n = 16 (262144 cells), the register FFT of the
+    collision kernels against the DFT as FP32 matrix-core products: one forward
+    transform per cell (I/O bound) and 17 (8 inverse-forward round trips in
+    registers, as compute-bound as the fused evaluation); and the O(n^4)
+    pseudo-spectral FP64 form against the fast path on 1024 cells."""
+    out = {}
+    B = 1 << 18
+    base = workloads.two_maxwellians_batch(4300, 256, 16, noise=0.05)
+    f = torch.from_numpy(np.ascontiguousarray(np.tile(base, (B // 256, 1, 1)))).cuda()
+    st = {}
+    for m, name in ((0, "register_fft"), (1, "mfma_dft")):
+        for reps in (0, 8):
+            t = time_calls(lambda: qdvm.transform_stage(f, m, reps), max(5, args.steps // 5), 2)
+            st["%s_transforms_%d_ms" % (name, 2 * reps + 1)] = t
+    per_fft = (st["register_fft_transforms_17_ms"] - st["register_fft_transforms_1_ms"]) / 16
+    per_mfma = (st["mfma_dft_transforms_17_ms"] - st["mfma_dft_transforms_1_ms"]) / 16
+    st.update({"cells": B, "ms_per_transform_register_fft": per_fft, "ms_per_transform_mfma_dft": per_mfma,
+               "mfma_over_fft": per_mfma / per_fft})
+    out["transform_stage_2d_n16"] = st
+    log("transform stage 2D n=16, %d cells: FFT %.4f ms, MFMA DFT %.4f ms per transform (x%.2f)"
+        % (B, per_fft, per_mfma, per_mfma / per_fft))
+    pl = qdvm.Plan(2, 16, 8.0, farey_order=4)
+    g = f[:1024].contiguous()
+    tp = time_calls(lambda: pl.eval_pseudo_spectral(g), 3, 1)
+    tf = time_calls(lambda: pl.eval(g), 10, 2)
+    out["pseudo_spectral_2d_n16_order4"] = {"cells": 1024, "ms": tp, "fast_path_ms": tf, "ratio": tp / tf,
+                                            "note": "O(n^4) FP64 direct sums (Sec. 3.1) vs the O(P n^2 log n) FP32 path"}
+    log("pseudo-spectral 2D n=16 order 4, 1024 cells: %.3f ms (fast path %.4f ms)" % (tp, tf))
+    pl.close()
+    return out
+
+
 def profile_workload(args, qdvm, workloads, torch):
     """One secondary workload alone: 3D n=32 P=16 on 2048 cells, its adjoint on
     the 64-cell differentiation batch, the adjoint and the near-equilibrium
@@ -470,6 +503,7 @@ def main():
             pl.close()
         del f3, q3
         torch.cuda.empty_cache()
+        results.update(transform_choice(qdvm, workloads, torch, args))
         results.update(batched_step(qdvm, workloads, torch, args))
         results.update(adaptive_step(qdvm, workloads, torch, args))
 

@@ -354,6 +354,39 @@ qdvm_status qdvm_get_variant(qdvm_plan_t plan, int32_t op, int32_t* variant);
  */
 qdvm_status qdvm_autotune(qdvm_plan_t plan, int32_t batch, hipStream_t stream);
 
+/*
+ * Q(f, f) by the pseudo-spectral form of Sec. 3.1: q~_I = sum_{K+L=I}
+ * (beta(K, L) - beta(L, L)) f~_K f~_L with the kernel modes of eq. (3.2),
+ * beta(K, L) = sum_p w_p alpha_p(K) alpha'_p(L) under the plan's direction
+ * set, weights and line-weight profile, evaluated by direct O(n^{2d}) sums in
+ * FP64 on the device (forward DFT, mode sum, inverse DFT): an independent
+ * second evaluation of the plan's operator for small grids, to check the
+ * fast FP32 path against on the GPU.  2D n <= 32 and 3D n = 8 (EUNSUPPORTED
+ * otherwise).  f, q device, batch * n^d floats; q must not alias f.  The
+ * first call on a plan builds its n^{2d} FP64 table of modes on the host,
+ * uploads it (allocates) and synchronises; later calls are asynchronous.
+ * The plan's mode and the evaluation's launch shape do not apply.
+ */
+qdvm_status qdvm_eval_pseudo_spectral(qdvm_plan_t plan, int32_t batch, const float* f, float* q,
+                                      hipStream_t stream);
+
+/*
+ * The forward transform of the 2D evaluation as a stage by itself, for
+ * measuring the choice of transform (Sec. 3.1: the operator lives on the DFT
+ * of f): fhat[cell][K1][K0] = sum_j f[cell][j0][j1] exp(-2 pi i (K.j) / n),
+ * complex FP32 pairs, for `batch` real n x n cells (device pointers, cells
+ * back to back).  method 0: the register FFT the collision kernels run;
+ * method 1: the DFT as dense products on the FP32 matrix cores (MFMA).
+ * reps (0..64): inverse-forward round trips on the spectrum in registers
+ * before it is written (each scaled back by 1/n^2, so the result is the same
+ * transform up to rounding): with reps > 0 the stage costs 2 reps + 1
+ * transforms per cell for one read and one write, as the transforms of the
+ * fused evaluation do.  Only dim = 2, n = 16 (EUNSUPPORTED otherwise).  The
+ * evaluation itself always uses the FFT (the measured faster of the two).
+ */
+qdvm_status qdvm_transform_stage(int32_t method, int32_t dim, int32_t n, int32_t batch, int32_t reps,
+                                 const float* f, float* fhat, hipStream_t stream);
+
 const char* qdvm_status_string(qdvm_status status);
 /* Detail of the last error raised on the calling thread ("" if none). */
 const char* qdvm_last_error(void);

@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", CSRC, "-I", INCLUDE, "-Wall", "-Wn
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = [("capi.cpp", False), ("plan.cpp", False), ("kernels_2d.hip", True), ("kernels_3d.hip", True),
-           ("kernels_batched.hip", True), ("noalloc.hip", True)]
+           ("kernels_batched.hip", True), ("noalloc.hip", True), ("stage.hip", True), ("pseudo.hip", True)]
 
 
 def _hipcc():

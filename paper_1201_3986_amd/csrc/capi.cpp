@@ -119,6 +119,8 @@ void free_device(qdvm::HostPlan& hp)
     hipFree(hp.d_lamb0);
     hipFree(hp.d_dirw0);
     hipFree(hp.d_ws);
+    hipFree(hp.d_beta);
+    hp.d_beta = nullptr;
     hp.d_jobs = nullptr;
     hp.d_dirichlet = nullptr;
     hp.d_aperp = nullptr;
@@ -1112,6 +1114,51 @@ qdvm_status qdvm_step_graph_destroy(qdvm_graph_t g)
     const hipError_t e = hipDeviceSynchronize();
     free_graph(g);
     return from_hip(e, "destroying the step graph");
+}
+
+qdvm_status qdvm_eval_pseudo_spectral(qdvm_plan_t p, int32_t batch, const float* f, float* q, hipStream_t stream)
+{
+    if (!p) return fail(QDVM_EINVAL, "null plan");
+    if (batch < 0) return fail(QDVM_EINVAL, "negative batch");
+    if (!qdvm::pseudo_supported(p->hp.dim, p->hp.n))
+        return fail(QDVM_EUNSUPPORTED, "the pseudo-spectral form is built for 2D n <= 32 and 3D n = 8");
+    if (batch == 0) return QDVM_OK;
+    if (!f || !q) return fail(QDVM_EINVAL, "null f or q");
+    if (f == q) return fail(QDVM_EINVAL, "q must not alias f");
+    std::lock_guard<std::mutex> lock(p->mu);
+    qdvm_status s = check_device(p);
+    if (s != QDVM_OK) return s;
+    qdvm::HostPlan& hp = p->hp;
+    if (!hp.d_beta) {
+        std::vector<double> beta;
+        try {
+            beta = qdvm::build_pseudo_modes(hp);
+        } catch (const std::bad_alloc&) {
+            return fail(QDVM_ENOMEM, "host allocation failed while building the kernel modes");
+        }
+        double* d = nullptr;
+        hipError_t e = upload(&d, beta);
+        if (e != hipSuccess) {
+            hipFree(d);
+            return from_hip(e, "uploading the kernel modes");
+        }
+        hp.d_beta = d;
+    }
+    return from_hip(qdvm::launch_pseudo(hp.dim, hp.n, batch, hp.d_beta, f, q, stream),
+                    "launching the pseudo-spectral kernel");
+}
+
+qdvm_status qdvm_transform_stage(int32_t method, int32_t dim, int32_t n, int32_t batch, int32_t reps,
+                                 const float* f, float* fhat, hipStream_t stream)
+{
+    if (method != 0 && method != 1) return fail(QDVM_EINVAL, "method must be 0 (register FFT) or 1 (matrix-core DFT)");
+    if (reps < 0 || reps > 64) return fail(QDVM_EINVAL, "reps must be in [0, 64]");
+    if (batch < 0) return fail(QDVM_EINVAL, "negative batch");
+    if (dim != 2 || n != 16) return fail(QDVM_EUNSUPPORTED, "the transform stage is built for 2D n = 16 only");
+    if (batch == 0) return QDVM_OK;
+    if (!f || !fhat) return fail(QDVM_EINVAL, "null f or fhat");
+    return from_hip(qdvm::launch_transform_stage(method, batch, reps, f, (float2*)fhat, stream),
+                    "launching the transform stage");
 }
 
 const char* qdvm_status_string(qdvm_status s)

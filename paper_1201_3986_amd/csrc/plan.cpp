@@ -268,4 +268,74 @@ std::string build_host_plan(int dim, int n, double half_width, int ntilde, int f
     return std::string();
 }
 
+bool pseudo_supported(int dim, int n) { return (dim == 2 && n <= 32) || (dim == 3 && n == 8); }
+
+// Kernel modes of the pseudo-spectral form (Sec. 3.1, eq. (3.2)) under the
+// direction decomposition: beta(K, L) = sum_p w_p alpha_p(K) alpha'_p(L) with
+// the line multiplier alpha_p(K) = sum_{0<|m|<=M_p} rho(m) cos(2 pi m e_p.K / n)
+// and the plane multiplier alpha'_p(L) = sum_{l.e_p = 0, |l|_inf <= Nt} cos(2 pi L.l / n);
+// beta~(K, L) = beta(K, L) - beta(L, L).  Indices in C order.
+std::vector<double> build_pseudo_modes(const HostPlan& hp)
+{
+    const int d = hp.dim, n = hp.n, nt = hp.ntilde;
+    int npts = 1;
+    for (int a = 0; a < d; ++a) npts *= n;
+    std::vector<double> ct(n);
+    for (int r = 0; r < n; ++r) ct[r] = std::cos(2.0 * M_PI * r / n);
+    auto coord = [&](int idx, int* c) {
+        for (int a = d - 1; a >= 0; --a) {
+            c[a] = idx % n;
+            idx /= n;
+        }
+    };
+    std::vector<double> beta((size_t)npts * npts, 0.0), al(npts), ap(npts);
+    for (int p = 0; p < hp.P; ++p) {
+        const int M = hp.M[p];
+        if (M < 1) continue;
+        const int* e = &hp.dirs[(size_t)p * d];
+        std::vector<std::array<int, 3>> plane;
+        const int side = 2 * nt + 1;
+        int total = 1;
+        for (int a = 0; a < d; ++a) total *= side;
+        for (int idx = 0; idx < total; ++idx) {
+            std::array<int, 3> l{0, 0, 0};
+            int r = idx, dot = 0;
+            for (int a = d - 1; a >= 0; --a) {
+                l[a] = r % side - nt;
+                r /= side;
+            }
+            for (int a = 0; a < d; ++a) dot += l[a] * e[a];
+            if (dot == 0) plane.push_back(l);
+        }
+        for (int K = 0; K < npts; ++K) {
+            int kc[3] = {0, 0, 0};
+            coord(K, kc);
+            int s = 0;
+            for (int a = 0; a < d; ++a) s += e[a] * kc[a];
+            s = ((s % n) + n) % n;
+            double A = 0.0;
+            for (int m = 1; m <= M; ++m) A += 2.0 * ct[(m * s) % n] / (hp.line_weight ? (double)m : 1.0);
+            al[K] = A;
+            double B = 0.0;
+            for (const auto& l : plane) {
+                int t = 0;
+                for (int a = 0; a < d; ++a) t += kc[a] * l[a];
+                B += ct[((t % n) + n) % n];
+            }
+            ap[K] = B;
+        }
+        const double w = (double)(float)hp.weights[p];
+        for (int K = 0; K < npts; ++K) {
+            const double wa = w * al[K];
+            double* row = &beta[(size_t)K * npts];
+            for (int L = 0; L < npts; ++L) row[L] += wa * ap[L];
+        }
+    }
+    std::vector<double> diag(npts);
+    for (int L = 0; L < npts; ++L) diag[L] = beta[(size_t)L * npts + L];
+    for (int K = 0; K < npts; ++K)
+        for (int L = 0; L < npts; ++L) beta[(size_t)K * npts + L] -= diag[L];
+    return beta;
+}
+
 }  // namespace qdvm

@@ -76,6 +76,9 @@ struct HostPlan {
     int device = 0;
     // workspace, allocated with the plan and sized for every batch (max_slots)
     void* d_ws = nullptr;
+    // kernel modes beta~(K, L) of the pseudo-spectral form, [K][L], FP64, built
+    // on the first pseudo-spectral evaluation (small grids only)
+    double* d_beta = nullptr;
     size_t ws_bytes = 0;
     int npts() const { int t = 1; for (int a = 0; a < dim; ++a) t *= n; return t; }
     DevPlan dev() const
@@ -101,6 +104,12 @@ std::string build_host_plan(int dim, int n, double half_width, int ntilde, int f
                             HostPlan& hp);
 
 bool supported_size(int dim, int n);
+
+// Grids the pseudo-spectral evaluation supports (n^{2d} table): 2D n <= 32, 3D n = 8.
+bool pseudo_supported(int dim, int n);
+// beta~(K, L) = beta(K, L) - beta(L, L), beta(K, L) = sum_p w_p alpha_p(K) alpha'_p(L),
+// in FP64 with the weights rounded to FP32 as the device kernels see them.
+std::vector<double> build_pseudo_modes(const HostPlan& hp);
 
 // ------------------------------------------------------------- launch API
 // Kernel-side launchers (kernels.hip).  All return hipSuccess or an error.
@@ -225,6 +234,14 @@ qdvm_status eval_with_scratch(qdvm_plan_s* p, int32_t batch, const float* f, flo
                               hipStream_t stream, void* ws, size_t ws_bytes);
 // Sets the calling thread's last-error text and returns st.
 qdvm_status record_error(qdvm_status st, const char* msg);
+
+// Pseudo-spectral evaluation (pseudo.hip): q = Q(f, f) from the FP64 table beta~.
+hipError_t launch_pseudo(int dim, int n, int batch, const double* beta, const float* f, float* q, hipStream_t st);
+
+// Forward 2D transform stage at n = 16 (stage.hip): method 0 register FFT,
+// 1 DFT as FP32 matrix-core products; `reps` inverse-forward round trips in
+// between; out[cell][K1][K0] = fhat(K0, K1).
+hipError_t launch_transform_stage(int method, int batch, int reps, const float* f, float2* out, hipStream_t st);
 
 int num_variants(int dim, int n);
 int default_variant(int dim, int n);

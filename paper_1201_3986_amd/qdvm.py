@@ -72,6 +72,8 @@ def load():
             "qdvm_vjp": [vp, i32, vp, vp, vp, vp, vp, vp],
             "qdvm_eval_noalloc": [vp, i32, vp, vp, vp, ctypes.c_float, vp],
             "qdvm_eval_bilinear": [vp, i32, vp, vp, vp, vp, ctypes.c_float, vp],
+            "qdvm_transform_stage": [i32, i32, i32, i32, i32, vp, vp, vp],
+            "qdvm_eval_pseudo_spectral": [vp, i32, vp, vp, vp],
             "qdvm_set_variant": [vp, i32, i32],
             "qdvm_get_variant": [vp, i32, i32p],
             "qdvm_autotune": [vp, i32, vp],
@@ -262,6 +264,17 @@ class Plan:
         w = self._weights(w)
         _check(load().qdvm_eval_bilinear(self._h, batch, _ptr(g), _ptr(f), _ptr(out), _ptr(w), float(dt),
                                          _stream_ptr(stream)))
+        return out
+
+    def eval_pseudo_spectral(self, f, out=None, stream=None):
+        """Q(f, f) by the O(n^2d) pseudo-spectral form in FP64 (2D n <= 32, 3D n = 8)."""
+        import torch
+        batch = self._cells(f, "f")
+        if out is None:
+            out = torch.empty_like(f)
+        elif self._cells(out, "out") != batch:
+            raise ValueError("out and f differ in size")
+        _check(load().qdvm_eval_pseudo_spectral(self._h, batch, _ptr(f), _ptr(out), _stream_ptr(stream)))
         return out
 
     def eval_noalloc(self, f, out, w=None, dt=0.0, stream=None):
@@ -457,6 +470,23 @@ def eval_batched(plans, offsets, f, out, dt=0.0, stream=None):
     _check(load().qdvm_eval_batched(len(plans), _plan_array(plans),
                                     offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                     _ptr(f), _ptr(out), float(dt), _stream_ptr(stream)))
+    return out
+
+
+def transform_stage(f, method=0, reps=0, stream=None):
+    """Forward 2D transform of n = 16 cells (f: float32 CUDA, batch * 256) as
+    complex spectra out[cell][K1][K0] (complex64 CUDA tensor); method 0 the
+    register FFT, 1 the matrix-core DFT; reps inverse-forward round trips in
+    registers before the spectrum is written."""
+    import torch
+    if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float32 or not f.is_contiguous():
+        raise TypeError("f must be a contiguous float32 CUDA tensor")
+    if f.numel() % 256:
+        raise ValueError("f is not a whole number of 16 x 16 cells")
+    batch = f.numel() // 256
+    out = torch.empty(batch, 16, 16, dtype=torch.complex64, device=f.device)
+    _check(load().qdvm_transform_stage(int(method), 2, 16, batch, int(reps), _ptr(f), _ptr(out),
+                                       _stream_ptr(stream)))
     return out
 
 
