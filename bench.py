@@ -407,10 +407,12 @@ def main():
         for order in (8, 14):
             pl = qdvm.Plan(2, 64, 8.0, farey_order=order)
             t = time_calls(lambda: pl.eval(f, out=q), 5, 1)
-            e = sampled_error(pl, f_np, q.cpu().numpy(), range(0, n_check, 4))
+            e = sampled_error(pl, f_np, q.cpu().numpy(), range(n_check))
             results["2d_n64_order%d" % order] = {
                 "lines": pl.num_dirs, "cells_per_s": B / (t * 1e-3), "ms": t, "rel_err": e,
-                "rel_err_cells": len(range(0, n_check, 4)),
+                "rel_err_cells": n_check, "meets_1e-5": e <= 1e-5,
+                "note": "whole line set, not a configuration of the sweep; FP32 limit on the cells whose gain "
+                        "and loss are ~33 max|Q| at the peak",
                 "tflops": algorithmic_flops(2, 64, pl.num_jobs) * B / (t * 1e-3) / 1e12}
             log("2D n=64 Farey order %d (%d lines): %.3f ms, rel err %.2e" % (order, pl.num_dirs, t, e))
             pl.close()

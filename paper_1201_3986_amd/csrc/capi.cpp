@@ -166,8 +166,10 @@ WsLayout ws_layout(const qdvm::HostPlan& hp, size_t slots, size_t rows, size_t p
     // job weights, or the per-direction weights of the bilinear operator
     L.jobw = off; off = align_up(off + sizeof(float) * std::max<size_t>(njobs, (size_t)hp.P));
     L.spec = off; off = align_up(off + sizeof(float2) * npts * slots);
-    if (adjoint || kind == WS_BILINEAR || hp.mode) {
-        // adjoint: R; bilinear: the transform of g; near-equilibrium evaluation: g and a staging set
+    const bool flush = kind == WS_EVAL && hp.dim == 2 && hp.jobs.size() > (size_t)qdvm::kFlushJobs;
+    if (adjoint || kind == WS_BILINEAR || hp.mode || flush) {
+        // adjoint: R; bilinear: the transform of g; near-equilibrium evaluation: g and a staging set;
+        // 2D evaluation with many jobs: the compensated gain sums
         L.spec2 = off; off = align_up(off + sizeof(float2) * npts * slots * (kind == WS_EVAL ? 2 : 1));
     }
     if (adjoint) {
@@ -216,7 +218,7 @@ qdvm::DevScratch scratch_of(void* base, const qdvm::HostPlan& hp, const WsLayout
     s.lam = (float*)(b + L.lam);
     s.jobw = (float*)(b + L.jobw);
     s.spec = (float2*)(b + L.spec);
-    if (adjoint || kind == WS_BILINEAR || hp.mode) s.spec2 = (float2*)(b + L.spec2);
+    if (L.spec2) s.spec2 = (float2*)(b + L.spec2);   // laid out only where a launch uses it
     if (adjoint) {
         s.acc = (float2*)(b + L.acc);
         s.gw_part = (double*)(b + L.gw);
@@ -936,7 +938,10 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
             return from_hip(e == hipSuccess ? hipErrorInvalidValue : e, "configuring the batched kernel");
         }
         const size_t base_slot = qdvm::batched_slot_elems(fam);
-        const size_t slot_elems = any_split ? 3 * base_slot : base_slot;   // f, g and staging spectra
+        bool any_flush = false;   // 2D plans whose gain sums are flushed (cells_2d.h)
+        for (const auto& pp : F.plans) any_flush = any_flush || (pp.dim == 2 && pp.njobs > qdvm::kFlushJobs);
+        const size_t fslot = any_split ? 3 * base_slot : base_slot;          // f, g and staging spectra
+        const size_t slot_elems = fslot + (any_flush ? base_slot : 0);
         e = hipMalloc(&F.d_items, sizeof(qdvm::BatchItem) * F.items.size());
         if (e == hipSuccess) e = hipMemcpy(F.d_items, F.items.data(), sizeof(qdvm::BatchItem) * F.items.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMalloc(&F.d_cell_off, sizeof(int64_t) * F.cell_off.size());
@@ -959,6 +964,7 @@ qdvm_status qdvm_batch_plan(int32_t ncells, const qdvm_plan_t* cell_plan, const 
         F.dev.spec = F.d_spec;
         F.dev.slot_elems = (int64_t)slot_elems;
         F.dev.gslot = any_split ? (int64_t)base_slot : 0;
+        F.dev.fslot = any_flush ? (int64_t)fslot : 0;
         F.dev.fbytes = b->fbytes;
         F.dev.dtab_floats = (int32_t)dtab_floats;
         b->fams.push_back(F);
@@ -1240,7 +1246,10 @@ qdvm_status qdvm_adaptive_plan(int32_t ncells, const int64_t* cell_offset, int32
     std::vector<qdvm::DevPlan> plans;
     for (int32_t l = 0; l < nlevels; ++l) plans.push_back(level_plan[l]->hp.dev());
     const size_t base_slot = qdvm::batched_slot_elems(class_family(cls));
-    const size_t slot_elems = any_split ? 3 * base_slot : base_slot;   // f, g and staging spectra
+    bool any_flush = false;   // 2D plans whose gain sums are flushed (cells_2d.h)
+    for (const auto& pp : plans) any_flush = any_flush || (pp.dim == 2 && pp.njobs > qdvm::kFlushJobs);
+    const size_t fslot = any_split ? 3 * base_slot : base_slot;   // f, g and staging spectra
+    const size_t slot_elems = fslot + (any_flush ? base_slot : 0);
     e = hipMalloc(&a->d_cell_in, sizeof(int64_t) * ncells);
     if (e == hipSuccess) e = hipMemcpy(a->d_cell_in, cell_offset, sizeof(int64_t) * ncells, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&a->d_queue, sizeof(int64_t) * (size_t)nlevels * ncells);
@@ -1262,6 +1271,7 @@ qdvm_status qdvm_adaptive_plan(int32_t ncells, const int64_t* cell_offset, int32
     d.b.spec = a->d_spec;
     d.b.slot_elems = (int64_t)slot_elems;
     d.b.gslot = any_split ? (int64_t)base_slot : 0;
+    d.b.fslot = any_flush ? (int64_t)fslot : 0;
     d.b.fbytes = (uint32_t)(max_end * 4);
     d.b.dtab_floats = (int32_t)dtab_floats;
     d.cell_in = a->d_cell_in;

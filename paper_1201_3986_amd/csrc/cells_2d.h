@@ -126,10 +126,50 @@ __device__ __forceinline__ void job2d_multiply(float2 (&z)[N], const HalfSpec<N,
     }
 }
 
+// Gain accumulation over many jobs: the accumulator passes through values of
+// the size of the gain and loss terms (several times |Q|), and adding one
+// rounded product per job lets FP32 rounding grow with the number of jobs
+// (at 44 and 128 jobs it reaches 1e-5 of max|Q|).  With a sum buffer `rsc`
+// (per element a float pair: sum S, compensation C, at the spectral slot's
+// offsets), the accumulator is flushed every kFlushJobs jobs into S by
+// compensated (Kahan) addition and restarts from zero, so each FP32 partial
+// sum holds at most kFlushJobs (qdvm_internal.h) products; the result is S - C.
+
+template <int N>
+__device__ __forceinline__ void flush_gain(float (&acc)[N], rsrc_t rsc, int vspec, bool first)
+{
+    constexpr int RS2 = N * 8, C = N < 16 ? N : 16;
+#pragma unroll
+    for (int i0 = 0; i0 < N; i0 += C) {
+        float2 sc[C];
+        if (!first) {
+#pragma unroll
+            for (int i = 0; i < C; ++i) sc[i] = bload2(rsc, vspec, (i0 + i) * RS2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            float2 v;
+            if (first) {
+                v = make_float2(acc[i0 + i], 0.f);
+            } else {
+                const float y = acc[i0 + i] - sc[i].y;
+                const float t = sc[i].x + y;
+                v = make_float2(t, (t - sc[i].x) - y);
+            }
+            bstore2(v, rsc, vspec, (i0 + i) * RS2);
+            acc[i0 + i] = 0.f;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// rsc: the sum buffer of the flushed accumulation (used when flush is set,
+// i.e. when the plan has more than kFlushJobs jobs).
 template <int N, int RV>
 __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it, rsrc_t rlam,
                                             const float* __restrict__ jobw, float dt, bool valid, float* xb,
-                                            const float* dtab, int j)
+                                            const float* dtab, int j, rsrc_t rsc, bool flush)
 {
     constexpr int RS = N * 4;   // element stride in bytes
     float2 z[N];
@@ -169,6 +209,20 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
         inv2d<N, RV>(z, xb, j);
 #pragma unroll
         for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
+        if (flush && ((jb + 1) % kFlushJobs == 0 || jb + 1 == pl.njobs))
+            flush_gain<N>(acc, rsc, it.vspec, jb < kFlushJobs);
+    }
+    if (flush) {
+        constexpr int RS2 = N * 8, C = N < 16 ? N : 16;
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += C) {
+            float2 sc[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i) sc[i] = bload2(rsc, it.vspec, (i0 + i) * RS2);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < C; ++i) acc[i0 + i] = sc[i].x - sc[i].y;
+        }
     }
 
     if (!valid) return;

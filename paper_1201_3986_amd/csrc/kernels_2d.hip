@@ -49,9 +49,11 @@ __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const flo
     it.vcell = (local * NPTS + j) * 4;
     it.vspec = (local * NPTS + j) * 8;
     // near-equilibrium mode: the spectrum of g per slot (spec2 also holds a staging set, which
-    // these launches leave unused: at 256 threads both transforms of a job stay in registers)
+    // these launches leave unused: at 256 threads both transforms of a job stay in registers);
+    // plain mode with more than kFlushJobs jobs: the flushed gain sums (cell2d_eval)
     constexpr bool STAGE = false;
-    const rsrc_t rgh = make_rsrc(SPLIT ? s.spec2 + (size_t)blockIdx.x * CPB * NPTS : s.spec, CPB * NPTS * 8);
+    const rsrc_t rgh = make_rsrc((SPLIT || pl.njobs > kFlushJobs) ? s.spec2 + (size_t)blockIdx.x * CPB * NPTS : s.spec,
+                                 CPB * NPTS * 8);
     const rsrc_t rtg = make_rsrc(SPLIT ? s.spec2 + (size_t)(gridDim.x + blockIdx.x) * CPB * NPTS : s.spec,
                                  CPB * NPTS * 8);
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
@@ -62,7 +64,8 @@ __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const flo
         if constexpr (SPLIT && N != 64)   // n = 64: k_eval2d_pair
             cell2d_eval_split<N, RV, STAGE>(pl, it, rgh, rtg, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
         else if constexpr (!SPLIT)
-            cell2d_eval<N, RV>(pl, it, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
+            cell2d_eval<N, RV>(pl, it, rlam, s.jobw, dt, first + local < batch, xb, dtab, j, rgh,
+                               pl.njobs > kFlushJobs);
     }
 }
 

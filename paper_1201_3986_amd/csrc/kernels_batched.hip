@@ -75,7 +75,8 @@ __device__ __forceinline__ void batch_item_2d(const DevPlan& pl, const BatchItem
                                        make_rsrc(slot + 2 * b.gslot, (T / N) * NPTS * 8), rlam, pl.jobw0, dt,
                                        valid, xbase + local * N * (N + 1), dtab, j);
     else
-        cell2d_eval<N, 0>(pl, it, rlam, pl.jobw0, dt, valid, xbase + local * N * (N + 1), dtab, j);
+        cell2d_eval<N, 0>(pl, it, rlam, pl.jobw0, dt, valid, xbase + local * N * (N + 1), dtab, j,
+                          make_rsrc(slot + b.fslot, (T / N) * NPTS * 8), b.fslot != 0 && pl.njobs > kFlushJobs);
 }
 
 template <int N, int T, bool SPLIT>

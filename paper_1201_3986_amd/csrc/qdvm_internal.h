@@ -11,6 +11,10 @@
 
 namespace qdvm {
 
+// 2D evaluation with more jobs than this flushes its FP32 gain accumulator
+// every kFlushJobs jobs into a compensated sum in scratch memory (cells_2d.h).
+constexpr int kFlushJobs = 8;
+
 // One inverse transform of the direction loop ("job").  In 2D a line e and its
 // perpendicular e' give the same unit-weight term (Remark 3.5), so a job may
 // carry two directions, whose weights are added.
@@ -191,6 +195,8 @@ struct BatchDev {
     int64_t slot_elems;
     int64_t gslot;             // near-equilibrium plans: the spectrum of g at slot + gslot and a staging
                                // area at slot + 2 gslot (slot_elems = 3 gslot); else 0
+    int64_t fslot;             // 2D plans with more than kFlushJobs jobs: the compensated gain sums
+                               // (a float pair per point) at slot + fslot; else 0
     uint32_t fbytes;           // extent of f and q in bytes
     int32_t dtab_floats;       // LDS floats reserved for the Dirichlet tables (D and D - 1 rows)
 };
