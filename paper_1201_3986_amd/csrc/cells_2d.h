@@ -166,10 +166,117 @@ __device__ __forceinline__ void flush_gain(float (&acc)[N], rsrc_t rsc, int vspe
 
 // rsc: the sum buffer of the flushed accumulation (used when flush is set,
 // i.e. when the plan has more than kFlushJobs jobs).
-template <int N, int RV>
+// Per-job multiplier tables (JT launches).  Lane j of a 2D cell reads a row
+// of multipliers at (s_j + d k) mod n for k = 0..n-1: the line multiplier at
+// e.K (s_j = e0 j, d = e1) and the plane multiplier at e_perp.K (s_j = -e1 j,
+// d = e0).  With g = gcd(d, n), L = n / g and u = d / g (invertible mod L),
+// the walk stays in the coset r = s_j mod g and equals T_r(t_j + k) for
+//     T_r(t) = row((r + d t) mod n),  t_j = ((s_j - r) / g) u^{-1} mod L,
+// so a table of g rows of L + n entries lets every read sit at an immediate
+// offset k from the lane's own start, with no address arithmetic in the
+// loop.  A stride d = 0 (an axis direction) reads one entry per lane.  The
+// job weight cw = W_j / n^4 is folded in, split evenly between the real and
+// imaginary parts of the transform (sgn(cw) sqrt|cw| on the line row,
+// sqrt|cw| on the plane row), so the gain is accumulated as acc += g h.
+// n is a power of two here.
+struct JtWalk {
+    int d, g, L, uinv, size;
+};
+
+template <int N>
+__device__ __forceinline__ JtWalk jt_walk(int stride)
+{
+    JtWalk w;
+    w.d = modc<N>(stride);
+    if (w.d == 0) {
+        w.g = N; w.L = 1; w.uinv = 0; w.size = N;
+        return w;
+    }
+    w.g = w.d & -w.d;
+    w.L = N / w.g;
+    const uint32_t u = (uint32_t)(w.d / w.g);
+    uint32_t x = u;   // Newton steps (mod 2^32) for the inverse of an odd u modulo a power of two
+    x *= 2u - u * x;
+    x *= 2u - u * x;
+    x *= 2u - u * x;
+    w.uinv = (int)(x & (uint32_t)(w.L - 1));
+    w.size = w.g * (w.L + N);
+    return w;
+}
+
+// Table entry i of a walk: row index (r + d t) mod n with r = i / (L + n), t = i mod (L + n).
+template <int N>
+__device__ __forceinline__ int jt_row_index(const JtWalk& w, int i)
+{
+    if (w.d == 0) return i;
+    const int r = i / (w.L + N), t = i - r * (w.L + N);
+    return (r + w.d * t) & (N - 1);
+}
+
+// Lane start inside a walk's table.
+template <int N>
+__device__ __forceinline__ int jt_lane_start(const JtWalk& w, int s)
+{
+    if (w.d == 0) return s;
+    const int r = s & (w.g - 1);
+    const int t = ((s / w.g) * w.uinv) & (w.L - 1);
+    return r * (w.L + N) + t;
+}
+
+template <int N>
+__device__ __forceinline__ void build_job_table(float* jtab, const DevPlan& pl, const float* __restrict__ jobw,
+                                                int tid, int nthreads)
+{
+    const int arow0 = (pl.ntilde + 1) * N;
+    int off = 0;
+    for (int jb = 0; jb < pl.njobs; ++jb) {
+        const JobDesc J = gload(pl.jobs, jb);
+        const float cw = gload(jobw, jb);
+        const float sq = __builtin_sqrtf(__builtin_fabsf(cw));
+        const JtWalk wa = jt_walk<N>(J.e[1]), wb = jt_walk<N>(J.e[0]);
+        const float* arow = pl.dirichlet + arow0 + J.M * N;
+        const float* drow = pl.dirichlet + J.M * N;
+        const float sa = cw < 0.f ? -sq : sq;
+        for (int i = tid; i < wa.size; i += nthreads) jtab[off + i] = sa * gload(arow, jt_row_index<N>(wa, i));
+        off += wa.size;
+        for (int i = tid; i < wb.size; i += nthreads) jtab[off + i] = sq * gload(drow, jt_row_index<N>(wb, i));
+        off += wb.size;
+    }
+}
+
+// One job's spectral multiply from its tables: z(k) = (a + i b)(k) fhat(k);
+// BC: the walk of b has stride 0 (one entry for the lane).
+template <int N, bool BC>
+__device__ __forceinline__ void jt_multiply(float2 (&z)[N], const HalfSpec<N, N * 8>& hs, const float* pa,
+                                            const float* pb)
+{
+    const lds_fptr la = (lds_fptr)pa;
+    const lds_fptr lb = (lds_fptr)pb;
+    float b0 = 0.f;
+    if constexpr (BC) b0 = lb[0];
+    constexpr int C = N < 8 ? N : 8;   // spectrum loads in flight per chunk
+#pragma unroll
+    for (int k0 = 0; k0 < N; k0 += C) {
+        float2 F[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) F[i] = hs.get(k0 + i);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const float al = la[k0 + i], ap = BC ? b0 : lb[k0 + i];
+            z[k0 + i] = make_float2(__builtin_fmaf(al, F[i].x, -ap * F[i].y), __builtin_fmaf(al, F[i].y, ap * F[i].x));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// JT: the job loop reads the per-job tables (build_job_table) from jtab instead
+// of the shared Dirichlet rows of dtab (which it then does not touch).
+template <int N, int RV, bool JT = false>
 __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it, rsrc_t rlam,
                                             const float* __restrict__ jobw, float dt, bool valid, float* xb,
-                                            const float* dtab, int j, rsrc_t rsc, bool flush)
+                                            const float* dtab, int j, rsrc_t rsc, bool flush,
+                                            const float* jtab = nullptr)
 {
     constexpr int RS = N * 4;   // element stride in bytes
     float2 z[N];
@@ -202,13 +309,29 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
 
     // direction loop: g + i h = IFFT((alpha + i alpha') fhat), acc += W g h
     const float* atab = dtab_alpha(dtab, pl);
+    int jt_off = 0;
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = gload(pl.jobs, jb);
-        const float cw = gload(jobw, jb);
-        job2d_multiply<N, (N == 64 ? 0 : (N < 8 ? N : 8))>(z, fh, J, dtab, atab, j);
-        inv2d<N, RV>(z, xb, j);
+        if constexpr (JT) {
+            const JtWalk wa = jt_walk<N>(J.e[1]), wb = jt_walk<N>(J.e[0]);
+            const float* pa = jtab + jt_off + jt_lane_start<N>(wa, modc<N>(J.e[0] * j));
+            const float* pb = jtab + jt_off + wa.size + jt_lane_start<N>(wb, modc<N>(-J.e[1] * j));
+            jt_off += wa.size + wb.size;
+            // an axis job has one walk of stride 0; when it is the line walk the two swap
+            // roles (the transform then yields h + i g, and the gain g h is the same product)
+            if (wb.d == 0) jt_multiply<N, true>(z, fh, pa, pb);
+            else if (wa.d == 0) jt_multiply<N, true>(z, fh, pb, pa);
+            else jt_multiply<N, false>(z, fh, pa, pb);
+            inv2d<N, RV>(z, xb, j);
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
+            for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(z[i].x, z[i].y, acc[i]);
+        } else {
+            const float cw = gload(jobw, jb);
+            job2d_multiply<N, (N == 64 ? 0 : (N < 8 ? N : 8))>(z, fh, J, dtab, atab, j);
+            inv2d<N, RV>(z, xb, j);
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
+        }
         if (flush && ((jb + 1) % kFlushJobs == 0 || jb + 1 == pl.njobs))
             flush_gain<N>(acc, rsc, it.vspec, jb < kFlushJobs);
     }

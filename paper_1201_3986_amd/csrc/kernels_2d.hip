@@ -29,18 +29,22 @@
 namespace qdvm {
 
 // 256 threads, 256/n cells per workgroup item, persistent over items.  SPLIT
-// selects the near-equilibrium evaluation (second spectral buffer for g).
-template <int N, int RV, bool SPLIT>
+// selects the near-equilibrium evaluation (second spectral buffer for g); JT
+// (plain mode) gives every job its own weighted multiplier rows in LDS
+// (build_job_table) in place of the shared Dirichlet table.
+template <int N, int RV, bool SPLIT, bool JT = false>
 __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const float* f, float* q, float dt,
                                                 DevScratch s)
 {
+    static_assert(!(SPLIT && JT), "job tables serve the plain mode");
     constexpr int CPW = 64 / N, CPB = 4 * CPW, SLOT = N * (N + 1), NPTS = N * N;
     extern __shared__ float smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int j = lane % N, local = wave * CPW + lane / N;
     float* xb = smem + local * SLOT;
     float* dtab = smem + CPB * SLOT;
-    load_dtab(dtab, pl, tid, blockDim.x);
+    if constexpr (JT) build_job_table<N>(dtab, pl, s.jobw, tid, blockDim.x);
+    else load_dtab(dtab, pl, tid, blockDim.x);
     __syncthreads();
     const int nitems = (batch + CPB - 1) / CPB;
     const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
@@ -64,8 +68,8 @@ __global__ __launch_bounds__(256) void k_eval2d(DevPlan pl, int batch, const flo
         if constexpr (SPLIT && N != 64)   // n = 64: k_eval2d_pair
             cell2d_eval_split<N, RV, STAGE>(pl, it, rgh, rtg, rlam, s.jobw, dt, first + local < batch, xb, dtab, j);
         else if constexpr (!SPLIT)
-            cell2d_eval<N, RV>(pl, it, rlam, s.jobw, dt, first + local < batch, xb, dtab, j, rgh,
-                               pl.njobs > kFlushJobs);
+            cell2d_eval<N, RV, JT>(pl, it, rlam, s.jobw, dt, first + local < batch, xb, dtab, j, rgh,
+                                   pl.njobs > kFlushJobs, dtab);
     }
 }
 
@@ -176,6 +180,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 namespace {
 template <int N>
 size_t lds2d(int ntilde) { return sizeof(float) * ((size_t)(256 / N) * N * (N + 1) + (size_t)2 * (ntilde + 1) * N); }
+template <int N>
+size_t lds2d_jobs(int jt_floats) { return sizeof(float) * ((size_t)(256 / N) * N * (N + 1) + (size_t)jt_floats); }
 }  // namespace
 
 #define QDVM_SWITCH_2D(N_, ...)                          \
@@ -205,9 +211,30 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
         if (pl.mode)
             e = variant ? shaped_grid(k_eval2d<N, 1, true>, 256, li.lds, items, lim, li.grid)
                         : shaped_grid(k_eval2d<N, 0, true>, 256, li.lds, items, lim, li.grid);
-        else
-            e = variant ? shaped_grid(k_eval2d<N, 1, false>, 256, li.lds, items, lim, li.grid)
-                        : shaped_grid(k_eval2d<N, 0, false>, 256, li.lds, items, lim, li.grid);
+        else {
+            // n = 64: per-job tables when they fit in LDS and keep the occupancy of the
+            // shared rows (at smaller n the tables cost registers that lower occupancy)
+            if constexpr (N == 64) {
+                const size_t lds_jt = lds2d_jobs<N>(pl.jt_floats);
+                int full = 0, full_jt = 0;
+                e = variant ? occupancy_grid(k_eval2d<64, 1, false>, 256, li.lds, 1 << 30, full)
+                            : occupancy_grid(k_eval2d<64, 0, false>, 256, li.lds, 1 << 30, full);
+                if (e != hipSuccess) return e;
+                li.jt = lds_jt <= kMaxLds &&
+                        (variant ? occupancy_grid(k_eval2d<64, 1, false, true>, 256, lds_jt, 1 << 30, full_jt)
+                                 : occupancy_grid(k_eval2d<64, 0, false, true>, 256, lds_jt, 1 << 30, full_jt)) ==
+                            hipSuccess &&
+                        full_jt >= full;
+                if (li.jt) li.lds = lds_jt;
+            }
+            if (N == 64 && li.jt) {
+                e = variant ? shaped_grid(k_eval2d<64, 1, false, true>, 256, li.lds, items, lim, li.grid)
+                            : shaped_grid(k_eval2d<64, 0, false, true>, 256, li.lds, items, lim, li.grid);
+            } else {
+                e = variant ? shaped_grid(k_eval2d<N, 1, false>, 256, li.lds, items, lim, li.grid)
+                            : shaped_grid(k_eval2d<N, 0, false>, 256, li.lds, items, lim, li.grid);
+            }
+        }
         li.slots = li.grid * (256 / N);
     });
     return e;
@@ -224,6 +251,9 @@ hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q,
         } else if (pl.mode) {
             if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
             else hipLaunchKernelGGL((k_eval2d<N, 0, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+        } else if (N == 64 && li.jt) {
+            if (variant) hipLaunchKernelGGL((k_eval2d<64, 1, false, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+            else hipLaunchKernelGGL((k_eval2d<64, 0, false, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
         } else {
             if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
             else hipLaunchKernelGGL((k_eval2d<N, 0, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);

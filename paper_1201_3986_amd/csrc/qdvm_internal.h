@@ -14,6 +14,8 @@ namespace qdvm {
 // 2D evaluation with more jobs than this flushes its FP32 gain accumulator
 // every kFlushJobs jobs into a compensated sum in scratch memory (cells_2d.h).
 constexpr int kFlushJobs = 8;
+// LDS of one workgroup on gfx950 (bytes).
+constexpr size_t kMaxLds = 160 * 1024;
 
 // One inverse transform of the direction loop ("job").  In 2D a line e and its
 // perpendicular e' give the same unit-weight term (Remark 3.5), so a job may
@@ -24,6 +26,21 @@ struct JobDesc {
     int32_t p;      // direction index in the plan
     int32_t pp;     // paired perpendicular direction, or -1
 };
+
+// LDS floats of a 2D plan's per-job multiplier tables (the layout of
+// build_job_table in cells_2d.h): per job, a table for the line walk of
+// stride e1 and one for the plane walk of stride e0; a stride d = 0 mod n
+// takes n floats, else n + gcd(d, n) n (n a power of two).
+inline int jt_table_floats(const JobDesc* jobs, int njobs, int n)
+{
+    auto size = [n](int e) {
+        const int d = ((e % n) + n) % n;
+        return d == 0 ? n : n + (d & -d) * n;
+    };
+    int t = 0;
+    for (int jb = 0; jb < njobs; ++jb) t += size(jobs[jb].e[1]) + size(jobs[jb].e[0]);
+    return t;
+}
 
 // Device view of an immutable plan, passed to kernels by value.
 struct DevPlan {
@@ -40,6 +57,7 @@ struct DevPlan {
     const float* jobw0;          // [njobs] job weights / npts^2 for the default weights
     const float* lamb0;          // [npts] Lambda / npts of the bilinear operator (directions unpaired)
     const float* dirw0;          // [P] direction weights / npts^2 for the default weights
+    int32_t jt_floats;           // 2D: LDS floats of the per-job multiplier tables (cells_2d.h)
 };
 
 // Per-call scratch carved out of a plan's workspace.
@@ -97,6 +115,7 @@ struct HostPlan {
         d.jobw0 = d_jobw0;
         d.lamb0 = d_lamb0;
         d.dirw0 = d_dirw0;
+        d.jt_floats = dim == 2 ? jt_table_floats(jobs.data(), (int)jobs.size(), n) : 0;
         return d;
     }
 };
@@ -122,6 +141,7 @@ struct LaunchInfo {
     size_t lds = 0;
     int slots = 0;    // resident cell slots that need spectral scratch
     int jsplit = 1;   // > 1: each cell's direction loop is spread over jsplit workgroups
+    bool jt = false;  // 2D plain mode: per-job multiplier rows in LDS
 };
 
 // Launch shape of a kernel family, chosen by the autotuner or fixed by a
