@@ -319,7 +319,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--batch", type=int, default=16384, help="2D n=64 cells per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
@@ -375,7 +375,7 @@ def main():
         "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
         "traffic": (traffic * 1.0) if traffic is not None else None,
-        "kernel": "k_eval2d<64, 0, false> (one launch per step)",
+        "kernel": "k_eval2d<64, 0, false, true> (per-job multiplier tables; one launch per step)",
         "note": "FP32 vector peak counts packed (2-wide) FMA; this code is built without packed FP32 "
                 "instructions, so its own issue ceiling is half of it (78.6 TFLOP/s)",
         "algorithmic_flops_per_cell": algorithmic_flops(2, 64, plan.num_jobs),
