@@ -78,8 +78,15 @@ def recorded_traffic(name):
 
 
 def time_calls(fn, steps, warmup):
-    """Average ms per call, HIP events on the current stream (where the library launches)."""
+    """Average ms per call, HIP events on the current stream (where the library launches).
+    settle_s: before the warmup calls, repeat fn for that long, so that a measurement taken
+    after a stretch of host work (the GPU idle, its clocks down) starts at settled clocks."""
+    import time
     import torch
+    t0 = time.time()
+    while time.time() - t0 < settle_s:
+        fn()
+        torch.cuda.synchronize()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -286,28 +293,28 @@ def profile_workload(args, qdvm, workloads, torch):
         f3 = torch.from_numpy(np.ascontiguousarray(np.tile(base3, (32, 1, 1, 1)))).cuda()
         q3 = torch.empty_like(f3)
         pl = qdvm.Plan(3, 32, 8.0, num_dirs=16)
-        t = time_calls(lambda: pl.eval(f3, out=q3), args.steps, args.warmup)
+        t = time_calls(lambda: pl.eval(f3, out=q3), args.steps, args.warmup, settle_s=0.0)
         print(json.dumps({"workload": "3D n=32 P=16, 2048 cells", "ms": t}), flush=True)
     elif args.profile_workload == "vjp_3d_n32_p16":
         c5 = workloads.c5()
         fv = torch.from_numpy(c5["f"]).cuda()
         cv = torch.from_numpy(c5["cot"]).cuda()
         pl = qdvm.Plan(3, 32, 8.0, num_dirs=16)
-        t = time_calls(lambda: pl.vjp(fv, cv), args.steps, args.warmup)
+        t = time_calls(lambda: pl.vjp(fv, cv), args.steps, args.warmup, settle_s=0.0)
         print(json.dumps({"workload": "adjoint 3D n=32 P=16, 64 cells", "ms": t}), flush=True)
     elif args.profile_workload == "vjp_2d_n64_p16":
         base = workloads.two_maxwellians_batch(202, 64, 64, noise=0.05)
         f = torch.from_numpy(np.ascontiguousarray(np.tile(base, (256, 1, 1)))).cuda()
         cot = torch.from_numpy(np.random.default_rng(106).standard_normal(f.shape).astype(np.float32)).cuda()
         pl = qdvm.Plan(2, 64, 8.0, num_dirs=16)
-        t = time_calls(lambda: pl.vjp(f, cot), args.steps, args.warmup)
+        t = time_calls(lambda: pl.vjp(f, cot), args.steps, args.warmup, settle_s=0.0)
         print(json.dumps({"workload": "adjoint 2D n=64 P=16, 16384 cells", "ms": t}), flush=True)
     elif args.profile_workload == "near_2d_n64_p16":
         base = workloads.two_maxwellians_batch(202, 64, 64, noise=0.05)
         f = torch.from_numpy(np.ascontiguousarray(np.tile(base, (256, 1, 1)))).cuda()
         q = torch.empty_like(f)
         pl = qdvm.Plan(2, 64, 8.0, num_dirs=16, mode="near_equilibrium")
-        t = time_calls(lambda: pl.eval(f, out=q), args.steps, args.warmup)
+        t = time_calls(lambda: pl.eval(f, out=q), args.steps, args.warmup, settle_s=0.0)
         print(json.dumps({"workload": "near-equilibrium 2D n=64 P=16, 16384 cells", "ms": t}), flush=True)
     else:
         r = batched_step(qdvm, workloads, torch, args)
@@ -356,7 +363,7 @@ def main():
     q = torch.empty_like(f)
     plan = qdvm.Plan(2, 64, 8.0, num_dirs=16)
     log("headline: 2D n=64 P=16 jobs=%d batch=%d" % (plan.num_jobs, B))
-    ms = time_calls(lambda: plan.eval(f, out=q), args.steps, args.warmup)
+    ms = time_calls(lambda: plan.eval(f, out=q), args.steps, args.warmup, settle_s=0.0)
     pct = step_percentiles(lambda: plan.eval(f, out=q), min(args.steps, 50))
     value = B / (ms * 1e-3)
     flops = algorithmic_flops(2, 64, plan.num_jobs) * B
