@@ -77,7 +77,7 @@ def recorded_traffic(name):
     return float(m.group(1))
 
 
-def time_calls(fn, steps, warmup):
+def time_calls(fn, steps, warmup, settle_s=0.15):
     """Average ms per call, HIP events on the current stream (where the library launches).
     settle_s: before the warmup calls, repeat fn for that long, so that a measurement taken
     after a stretch of host work (the GPU idle, its clocks down) starts at settled clocks."""
