@@ -347,32 +347,68 @@ __global__ __launch_bounds__(256) void k_adapt_classify(AdaptDev a, const float*
 // 2D cells: one wave per cell, the cell held in registers (n^2 / 64 values per
 // lane, element e = lane + 64 k), wave-wide sums only.  A workgroup classifies
 // 64 cells and claims their queue places with one atomic per level (per-cell
-// atomics on a few counters serialise).
+// atomics on a few counters serialise).  n <= 32: 16 waves per workgroup (four
+// cells each), so that the grid of ncells / 64 workgroups fills four waves per
+// SIMD; n = 64 (a cell takes 64 registers per lane): four waves.
 template <int N>
-__global__ __launch_bounds__(256) void k_adapt_classify_2d(AdaptDev a, const float* __restrict__ f)
+constexpr int classify_threads() { return N <= 32 ? 1024 : 256; }
+
+template <int N>
+__global__ __launch_bounds__(classify_threads<N>()) void k_adapt_classify_2d(AdaptDev a, const float* __restrict__ f)
 {
-    constexpr int K = N * N / 64, CPB = 64;
+    constexpr int K = N * N / 64, CPB = 64, W = classify_threads<N>() / 64;
     __shared__ int s_lv[CPB];
     __shared__ int s_base[kMaxLevels];
+    __shared__ double s_e0[W][N];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c0 = blockIdx.x * CPB;
     const int nc = a.ncells - c0 < CPB ? a.ncells - c0 : CPB;
-    for (int j = wave; j < nc; j += 4) {
-        const int c = c0 + j;
-        const float* fc = f + a.cell_in[c];
-        float v[K];
+    // the reads of a wave's next cell go out before the current one is
+    // classified (each wave takes several cells in turn; their memory latency
+    // would otherwise add up)
+    // (n <= 32; at n = 64 the second copy of a cell does not fit in registers)
+    constexpr bool PF = K <= 16;
+    // the 64 cell offsets of the workgroup, one per lane (a cell's reads then
+    // wait for no offset read of their own); an adaptive plan keeps f below
+    // 2 GiB, so an element offset fits in 32 bits
+    const int off = lane < nc ? (int)a.cell_in[c0 + lane] : 0;
+    auto cell_ptr = [&](int jj) { return f + (uint32_t)__shfl(off, jj, 64); };
+    float vn[K];
+    if (PF && wave < nc) {
+        const float* fc = cell_ptr(wave);
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = fc[lane + 64 * k];
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, sq = 0.0;
+        for (int k = 0; k < K; ++k) vn[k] = fc[lane + 64 * k];
+    }
+    for (int j = wave; j < nc; j += W) {
+        const int c = c0 + j;
+        float v[K];
+        if constexpr (PF) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = vn[k];
+            if (j + W < nc) {
+                const float* fc = cell_ptr(j + W);
+#pragma unroll
+                for (int k = 0; k < K; ++k) vn[k] = fc[lane + 64 * k];
+            }
+        } else {
+            const float* fc = cell_ptr(j);
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = fc[lane + 64 * k];
+        }
+        // element e = lane + 64 k sits at i0 = h + (64 / n) k, i1 = lane mod n
+        // (n divides 64): the moments follow from three per-lane sums over k
+        constexpr int ST = 64 / N;
+        const int h = lane / N, i1 = lane % N;
+        double A = 0.0, B = 0.0, C = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int e = lane + 64 * k, i0 = e / N, i1 = e % N;
             const double x = v[k];
-            s0 += x;
-            s1 += i0 * x;
-            s2 += i1 * x;
-            sq += (double)(i0 * i0 + i1 * i1) * x;
+            A += x;
+            B = __builtin_fma((double)k, x, B);
+            C = __builtin_fma((double)(k * k), x, C);
         }
+        double s0 = A, s1 = __builtin_fma((double)ST, B, h * A), s2 = i1 * A;
+        double sq = (double)(h * h + i1 * i1) * A + (double)(2 * h * ST) * B + (double)(ST * ST) * C;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             s0 += __shfl_xor(s0, o, 64);
@@ -387,19 +423,21 @@ __global__ __launch_bounds__(256) void k_adapt_classify_2d(AdaptDev a, const flo
         const double norm = ok ? s0 / (2.0 * kPi * var) : 0.0;
         const double inv2v = ok ? 0.5 / var : 0.0;
         // M(i0, i1) = norm E0(i0) E1(i1): lane l computes E0(l mod n) and
-        // E1(l mod n) (two exps per lane).  i1 = e mod n = l mod n for every k,
-        // so E1 is the lane's own; E0(i0) comes from lane i0 by shuffle.
-        const int li = lane % N;
-        const double e0l = exp(-(li - m0) * (li - m0) * inv2v), e1 = exp(-(li - m1) * (li - m1) * inv2v);
+        // E1(l mod n) (two exps per lane).  E1 is the lane's own; the n values
+        // E0(i) go through a per-wave LDS row, read at immediate offsets.
+        const double e0l = exp(-(i1 - m0) * (i1 - m0) * inv2v), e1 = exp(-(i1 - m1) * (i1 - m1) * inv2v);
+        if (lane < N) s_e0[wave][lane] = e0l;
+        wave_sync();
+        const double* e0row = &s_e0[wave][h];
         double dsum = 0.0, fsum = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int e = lane + 64 * k, i0 = e / N;
             const double x = v[k];
-            const double M = ok ? norm * __shfl(e0l, i0, 64) * e1 : 0.0;
+            const double M = ok ? norm * e0row[ST * k] * e1 : 0.0;
             dsum += fabs(x - M);
             fsum += fabs(x);
         }
+        wave_sync();   // the row is rewritten for the wave's next cell
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             dsum += __shfl_xor(dsum, o, 64);
@@ -505,10 +543,10 @@ hipError_t launch_adaptive(const AdaptDev& a, const LaunchInfo& li, const float*
     hipLaunchKernelGGL(k_adapt_reset, dim3(1), dim3(64), 0, st, a.count);
     const unsigned w4 = (unsigned)((a.ncells + 63) / 64);   // 2D: 64 cells per workgroup
     switch (a.cls) {
-        case BC_2D8: hipLaunchKernelGGL((k_adapt_classify_2d<8>), dim3(w4), dim3(256), 0, st, a, f); break;
-        case BC_2D16: hipLaunchKernelGGL((k_adapt_classify_2d<16>), dim3(w4), dim3(256), 0, st, a, f); break;
-        case BC_2D32: hipLaunchKernelGGL((k_adapt_classify_2d<32>), dim3(w4), dim3(256), 0, st, a, f); break;
-        case BC_2D64: hipLaunchKernelGGL((k_adapt_classify_2d<64>), dim3(w4), dim3(256), 0, st, a, f); break;
+        case BC_2D8: hipLaunchKernelGGL((k_adapt_classify_2d<8>), dim3(w4), dim3(classify_threads<8>()), 0, st, a, f); break;
+        case BC_2D16: hipLaunchKernelGGL((k_adapt_classify_2d<16>), dim3(w4), dim3(classify_threads<16>()), 0, st, a, f); break;
+        case BC_2D32: hipLaunchKernelGGL((k_adapt_classify_2d<32>), dim3(w4), dim3(classify_threads<32>()), 0, st, a, f); break;
+        case BC_2D64: hipLaunchKernelGGL((k_adapt_classify_2d<64>), dim3(w4), dim3(classify_threads<64>()), 0, st, a, f); break;
         case BC_3D24: hipLaunchKernelGGL((k_adapt_classify<3, 24>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
         case BC_3D32: hipLaunchKernelGGL((k_adapt_classify<3, 32>), dim3(a.ncells), dim3(256), 0, st, a, f); break;
         default: return hipErrorInvalidValue;
