@@ -77,6 +77,47 @@ def recorded_traffic(name):
     return float(m.group(1))
 
 
+# algorithmic HBM bytes per cell of each secondary result: f in and Q out
+# (8 B per point), plus the second input of the bilinear form and the
+# cotangent of the adjoint (12 B per point)
+_RESULT_BYTES = {
+    "2d_n64_P8": 8 * 4096, "2d_n64_P32": 8 * 4096, "2d_n64_order8": 8 * 4096, "2d_n64_order14": 8 * 4096,
+    "2d_n64_P16": 8 * 4096, "2d_n64_P16_near_equilibrium": 8 * 4096, "bilinear_2d_n64_P16": 12 * 4096,
+    "vjp_2d_n64_P16": 12 * 4096, "3d_n32_P8": 8 * 32768, "3d_n32_P16": 8 * 32768,
+    "bilinear_3d_n32_P16": 12 * 32768, "vjp_3d_n32_P16_64cells": 12 * 32768,
+}
+
+
+def annotate_rooflines(results):
+    """Per secondary result: the share of the FP32 vector peak its algorithmic
+    FLOPs reach and its algorithmic HBM rate (the bound is the ALU for all)."""
+    for key, r in results.items():
+        if not isinstance(r, dict):
+            continue
+        if "tflops" in r:
+            r["frac_fp32_peak"] = round(r["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4)
+        if key in _RESULT_BYTES and "cells_per_s" in r:
+            gbs = _RESULT_BYTES[key] * r["cells_per_s"] / 1e9
+            r["hbm_gbs_algorithmic"] = round(gbs, 1)
+            r["hbm_frac_algorithmic"] = round(gbs / HBM_PEAK_GBS, 4)
+
+
+def platform_info(torch):
+    """GPU, HIP and torch versions of the run."""
+    info = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None)}
+    try:
+        info["gpu"] = torch.cuda.get_device_name(0)
+        info["cus"] = torch.cuda.get_device_properties(0).multi_processor_count
+    except Exception:  # noqa: BLE001 - informational only
+        pass
+    try:
+        with open("/opt/rocm/.info/version") as fh:
+            info["rocm"] = fh.read().strip()
+    except OSError:
+        pass
+    return info
+
+
 def time_calls(fn, steps, warmup, settle_s=0.15):
     """Average ms per call, HIP events on the current stream (where the library launches).
     settle_s: before the warmup calls, repeat fn for that long, so that a measurement taken
@@ -535,6 +576,7 @@ def main():
                "host": host_cpu()}
         log("cpu oracle: %.2f cells/s on %d threads" % (cells / dt, threads))
 
+    annotate_rooflines(results)
     out = {
         "metric": METRIC,
         "value": value,
@@ -559,6 +601,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "results": results,
+        "platform": platform_info(torch),
     }
     plan.close()
     print(json.dumps(out), flush=True)
