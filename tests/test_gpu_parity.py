@@ -127,6 +127,30 @@ def test_explicit_dirs_weights_and_call_weights(gpu_lib):
     assert np.array_equal(q3, q)
 
 
+def test_n64_job_tables_signed_and_zero_weights(gpu_lib):
+    """2D n = 64 plain plans fold each job's weight into its multiplier tables
+    (sgn(W) sqrt|W| on one row, sqrt|W| on the other).  Explicit lines with an
+    axis pair (a stride-0 walk), walks with gcd(stride, n) = 2, unpaired lines,
+    and call weights that make one pair's job weight negative and another's
+    zero, against the oracle."""
+    import torch
+    f = workloads.random_positive(64064, 2, 64, 5)
+    dirs = [[0, 1], [1, 0], [1, 2], [2, -1], [1, 1], [1, -1], [3, 1], [2, 3]]
+    plan = gpu_lib.Plan(2, 64, 8.0, dirs=dirs)
+    q = _eval(plan, f)
+    assert rel_linf(q, oracle_q(plan, f)) <= TOL
+    w = np.array([0.5, -0.8, 1.2, -1.2, 0.0, 0.3, -0.4, 0.9], dtype=np.float32) * plan.weights[0]
+    q2 = plan.eval(_dev(f), w=_dev(w))
+    torch.cuda.synchronize()
+    ref = oracle_q(plan, f, w=w)
+    # terms of opposite sign cancel in Q: the error is taken relative to the
+    # size of the terms, max |Q| under the weights |w|
+    scale = np.max(np.abs(oracle_q(plan, f, w=np.abs(w))))
+    err = np.max(np.abs(q2.cpu().numpy().reshape(-1) - ref.reshape(-1))) / scale
+    print("signed weights: error %.3e of max|Q(|w|)|" % err)
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("d,n,P", [(2, 32, 16), (3, 24, 16)])
 def test_euler_step_and_in_place(gpu_lib, d, n, P):
     import torch
