@@ -246,25 +246,37 @@ __device__ __forceinline__ void build_job_table(float* jtab, const DevPlan& pl, 
 
 // One job's spectral multiply from its tables: z(k) = (a + i b)(k) fhat(k);
 // BC: the walk of b has stride 0 (one entry for the lane).
+// Elements k and n - k are formed together: the lane reads its own half row
+// (k <= n/2) of the spectrum, and element n - k, the conjugate of the mirror
+// row's element k, comes by shuffle from the mirror lane (mlane), which has
+// just read it; the tables hold entry n - k at offset n - k.
 template <int N, bool BC>
 __device__ __forceinline__ void jt_multiply(float2 (&z)[N], const HalfSpec<N, N * 8>& hs, const float* pa,
-                                            const float* pb)
+                                            const float* pb, int mlane)
 {
     const lds_fptr la = (lds_fptr)pa;
     const lds_fptr lb = (lds_fptr)pb;
     float b0 = 0.f;
     if constexpr (BC) b0 = lb[0];
-    constexpr int C = N < 8 ? N : 8;   // spectrum loads in flight per chunk
+    constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;   // spectrum loads in flight per chunk
 #pragma unroll
-    for (int k0 = 0; k0 < N; k0 += C) {
+    for (int k0 = 0; k0 <= N / 2; k0 += C) {
         float2 F[C];
 #pragma unroll
-        for (int i = 0; i < C; ++i) F[i] = hs.get(k0 + i);
+        for (int i = 0; i < C; ++i)
+            if (k0 + i <= N / 2) F[i] = hs.get(k0 + i);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < C; ++i) {
-            const float al = la[k0 + i], ap = BC ? b0 : lb[k0 + i];
-            z[k0 + i] = make_float2(__builtin_fmaf(al, F[i].x, -ap * F[i].y), __builtin_fmaf(al, F[i].y, ap * F[i].x));
+            const int k = k0 + i;
+            if (k > N / 2) break;
+            const float al = la[k], ap = BC ? b0 : lb[k];
+            z[k] = make_float2(__builtin_fmaf(al, F[i].x, -ap * F[i].y), __builtin_fmaf(al, F[i].y, ap * F[i].x));
+            if (k >= 1 && k < N / 2) {
+                const float2 Fm = make_float2(__shfl(F[i].x, mlane, 64), -__shfl(F[i].y, mlane, 64));
+                const float bl = la[N - k], bp = BC ? b0 : lb[N - k];
+                z[N - k] = make_float2(__builtin_fmaf(bl, Fm.x, -bp * Fm.y), __builtin_fmaf(bl, Fm.y, bp * Fm.x));
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -319,9 +331,10 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
             jt_off += wa.size + wb.size;
             // an axis job has one walk of stride 0; when it is the line walk the two swap
             // roles (the transform then yields h + i g, and the gain g h is the same product)
-            if (wb.d == 0) jt_multiply<N, true>(z, fh, pa, pb);
-            else if (wa.d == 0) jt_multiply<N, true>(z, fh, pb, pa);
-            else jt_multiply<N, false>(z, fh, pa, pb);
+            const int mlane = (int)(threadIdx.x & 63) - j + ((N - j) & (N - 1));
+            if (wb.d == 0) jt_multiply<N, true>(z, fh, pa, pb, mlane);
+            else if (wa.d == 0) jt_multiply<N, true>(z, fh, pb, pa, mlane);
+            else jt_multiply<N, false>(z, fh, pa, pb, mlane);
             inv2d<N, RV>(z, xb, j);
 #pragma unroll
             for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(z[i].x, z[i].y, acc[i]);
@@ -899,18 +912,49 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
         const float cw = gload(jobw, jb);
         float spart = 0.f;
         {
+            // elements k and n - k together: the lane reads its own half row (k <= n/2)
+            // of the spectrum and of R; element n - k is the conjugate (for R the
+            // value) of the mirror row's element k, which the mirror lane has just
+            // read, so it comes by shuffle instead of a second read from memory.
+            // Forward walks for k, backward walks (from k = n - 1) for n - k.
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * j), modc<N>(J.e[1]));
             RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
+            RowWalk<N> am(atab + J.M * N, modc<N>(J.e[0] * j - J.e[1]), modc<N>(-J.e[1]));
+            RowWalk<N> bm(dtab + J.M * N, modc<N>(-J.e[1] * j - J.e[0]), modc<N>(-J.e[0]));
+            constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const float2 F = fh.get(k);
-                const float R = k <= N / 2 ? bload(rr, rown, k * RS) : bload(rr, rmir, (N - k) * RS);
-                const float al = a.get(), ap = b.get();
-                z[k] = make_float2(__builtin_fmaf(al, F.x, -ap * F.y), __builtin_fmaf(al, F.y, ap * F.x));
-                spart = __builtin_fmaf(al * ap, R, spart);
-                a.next();
-                b.next();
-                QDVM_CHUNK_FENCE(k);
+            for (int k0 = 0; k0 <= N / 2; k0 += C) {
+                float2 F[C];
+                float R[C];
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    if (k0 + i <= N / 2) {
+                        F[i] = bload2(it.fh, it.vspec, (k0 + i) * RS2);
+                        R[i] = bload(rr, rown, (k0 + i) * RS);
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const int k = k0 + i;
+                    if (k > N / 2) break;
+                    const float al = a.get(), ap = b.get();
+                    z[k] = make_float2(__builtin_fmaf(al, F[i].x, -ap * F[i].y),
+                                       __builtin_fmaf(al, F[i].y, ap * F[i].x));
+                    spart = __builtin_fmaf(al * ap, R[i], spart);
+                    a.next();
+                    b.next();
+                    if (k >= 1 && k < N / 2) {
+                        const float2 Fm = make_float2(__shfl(F[i].x, mlane, 64), -__shfl(F[i].y, mlane, 64));
+                        const float Rm = __shfl(R[i], mlane, 64);
+                        const float bl = am.get(), bp = bm.get();
+                        z[N - k] = make_float2(__builtin_fmaf(bl, Fm.x, -bp * Fm.y),
+                                               __builtin_fmaf(bl, Fm.y, bp * Fm.x));
+                        spart = __builtin_fmaf(bl * bp, Rm, spart);
+                        am.next();
+                        bm.next();
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         inv2d<N, RV>(z, xb, j);   // z = u + i v = n^2 (g + i h)
