@@ -438,6 +438,50 @@ __device__ __forceinline__ void cell2d_eval_bilinear(const DevPlan& pl, const It
             const int sp = modc<N>(-J.e[1] * j), dp = modc<N>(J.e[0]);
             RowWalk<N> a(atab + J.M * N, t ? sp : se, t ? dp : de);
             RowWalk<N> b(dtab + J.M * N, t ? se : sp, t ? de : dp);
+            if constexpr (N == 64) {
+                // elements k and n - k together: the lane reads its own half rows of
+                // both spectra; element n - k, the conjugate of the mirror row's
+                // element k, comes by shuffle from the mirror lane (backward walks)
+                const int mlane = (int)(threadIdx.x & 63) - j + ((N - j) & (N - 1));
+                RowWalk<N> am(atab + J.M * N, modc<N>((t ? sp : se) - (t ? dp : de)), modc<N>(-(t ? dp : de)));
+                RowWalk<N> bm(dtab + J.M * N, modc<N>((t ? se : sp) - (t ? de : dp)), modc<N>(-(t ? de : dp)));
+                constexpr int H = N / 2 + 1, CH = 8;
+#pragma unroll
+                for (int k0 = 0; k0 < H; k0 += CH) {
+                    float2 G[CH], F[CH];
+#pragma unroll
+                    for (int i = 0; i < CH; ++i)
+                        if (k0 + i < H) {
+                            G[i] = gh.get(k0 + i);
+                            F[i] = fh.get(k0 + i);
+                        }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int i = 0; i < CH; ++i) {
+                        const int k = k0 + i;
+                        if (k >= H) break;
+                        const float al = a.get(), ap = b.get();
+                        z[k] = make_float2(__builtin_fmaf(al, G[i].x, -ap * F[i].y),
+                                           __builtin_fmaf(al, G[i].y, ap * F[i].x));
+                        a.next();
+                        b.next();
+                        if (k >= 1 && k < N / 2) {
+                            const float2 Gm = make_float2(__shfl(G[i].x, mlane, 64), -__shfl(G[i].y, mlane, 64));
+                            const float2 Fm = make_float2(__shfl(F[i].x, mlane, 64), -__shfl(F[i].y, mlane, 64));
+                            const float bl = am.get(), bp = bm.get();
+                            z[N - k] = make_float2(__builtin_fmaf(bl, Gm.x, -bp * Fm.y),
+                                                   __builtin_fmaf(bl, Gm.y, bp * Fm.x));
+                            am.next();
+                            bm.next();
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                inv2d<N, RV>(z, xb, j);
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
+                continue;
+            }
             // chunks of 8 elements of both spectra, all read before the chunk's
             // multiply (at n = 64 chunks of 2 left most of each read's latency
             // exposed: 2.53 against 1.96 ms for 16384 cells at P = 16)
