@@ -212,24 +212,28 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
             e = variant ? shaped_grid(k_eval2d<N, 1, true>, 256, li.lds, items, lim, li.grid)
                         : shaped_grid(k_eval2d<N, 0, true>, 256, li.lds, items, lim, li.grid);
         else {
-            // n = 64: per-job tables when they fit in LDS and keep the occupancy of the
-            // shared rows (at smaller n the tables cost registers that lower occupancy)
-            if constexpr (N == 64) {
+            // n = 64 and 32: per-job tables when they fit in LDS and either keep the
+            // occupancy of the shared rows (n = 64) or the batch fills at least two
+            // rounds of the persistent grid (n = 32: the tables cost registers, one
+            // wave per SIMD fewer, which measured slower at 4096 cells, 0.047 against
+            // 0.042 ms, and faster at 32768, 0.278 against 0.297 ms)
+            if constexpr (N == 64 || N == 32) {
                 const size_t lds_jt = lds2d_jobs<N>(pl.jt_floats);
-                int full = 0, full_jt = 0;
-                e = variant ? occupancy_grid(k_eval2d<64, 1, false>, 256, li.lds, 1 << 30, full)
-                            : occupancy_grid(k_eval2d<64, 0, false>, 256, li.lds, 1 << 30, full);
-                if (e != hipSuccess) return e;
-                li.jt = lds_jt <= kMaxLds &&
-                        (variant ? occupancy_grid(k_eval2d<64, 1, false, true>, 256, lds_jt, 1 << 30, full_jt)
-                                 : occupancy_grid(k_eval2d<64, 0, false, true>, 256, lds_jt, 1 << 30, full_jt)) ==
-                            hipSuccess &&
-                        full_jt >= full;
-                if (li.jt) li.lds = lds_jt;
+                if (lim.allow_jt && lds_jt <= kMaxLds) {
+                    int full = 0, full_jt = 0;
+                    e = variant ? occupancy_grid(k_eval2d<N, 1, false>, 256, li.lds, 1 << 30, full)
+                                : occupancy_grid(k_eval2d<N, 0, false>, 256, li.lds, 1 << 30, full);
+                    if (e != hipSuccess) return e;
+                    li.jt = (variant ? occupancy_grid(k_eval2d<N, 1, false, true>, 256, lds_jt, 1 << 30, full_jt)
+                                     : occupancy_grid(k_eval2d<N, 0, false, true>, 256, lds_jt, 1 << 30,
+                                                      full_jt)) == hipSuccess &&
+                            (full_jt >= full || items >= 2 * full_jt);
+                    if (li.jt) li.lds = lds_jt;
+                }
             }
-            if (N == 64 && li.jt) {
-                e = variant ? shaped_grid(k_eval2d<64, 1, false, true>, 256, li.lds, items, lim, li.grid)
-                            : shaped_grid(k_eval2d<64, 0, false, true>, 256, li.lds, items, lim, li.grid);
+            if ((N == 64 || N == 32) && li.jt) {
+                e = variant ? shaped_grid(k_eval2d<N, 1, false, true>, 256, li.lds, items, lim, li.grid)
+                            : shaped_grid(k_eval2d<N, 0, false, true>, 256, li.lds, items, lim, li.grid);
             } else {
                 e = variant ? shaped_grid(k_eval2d<N, 1, false>, 256, li.lds, items, lim, li.grid)
                             : shaped_grid(k_eval2d<N, 0, false>, 256, li.lds, items, lim, li.grid);
@@ -251,9 +255,9 @@ hipError_t launch_eval2d(const DevPlan& pl, int batch, const float* f, float* q,
         } else if (pl.mode) {
             if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
             else hipLaunchKernelGGL((k_eval2d<N, 0, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
-        } else if (N == 64 && li.jt) {
-            if (variant) hipLaunchKernelGGL((k_eval2d<64, 1, false, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
-            else hipLaunchKernelGGL((k_eval2d<64, 0, false, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+        } else if ((N == 64 || N == 32) && li.jt) {
+            if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, false, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
+            else hipLaunchKernelGGL((k_eval2d<N, 0, false, true>), g, b, li.lds, st, pl, batch, f, q, dt, s);
         } else {
             if (variant) hipLaunchKernelGGL((k_eval2d<N, 1, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);
             else hipLaunchKernelGGL((k_eval2d<N, 0, false>), g, b, li.lds, st, pl, batch, f, q, dt, s);

@@ -560,6 +560,15 @@ int max_slots(const DevPlan& pl, int op, int variant, int threads)
                                              : bilinear_launch_info(pl, big, variant, lim));
     if (li.grid <= 0) return 0;
     int slots = li.slots;
+    if (op == 0 && pl.dim == 2 && !pl.mode) {
+        // a 2D evaluation takes the per-job tables for large batches only: a
+        // smaller batch may fill the (larger) grid of the shared-row kernel
+        LaunchLimits rows = lim;
+        rows.allow_jt = false;
+        const LaunchInfo lr = eval_launch_info(pl, big, variant, rows);
+        if (lr.grid <= 0) return 0;
+        slots = std::max(slots, lr.slots);
+    }
     if (pl.dim == 3 && op != 2 && !(op == 0 && pl.mode)) {
         // direction-split launches: one slot per workgroup, up to the split kernel's occupancy
         int cap = 0;

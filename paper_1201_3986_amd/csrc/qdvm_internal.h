@@ -157,6 +157,7 @@ struct LaunchLimits {
     int split = 0;
     int grid_div = 1;
     int threads = 0;
+    bool allow_jt = true;   // 2D plain evaluation: per-job multiplier tables may be chosen
 };
 // true where a 3D grid size has an alternative workgroup size (n = 16, 32)
 bool has_alt_threads(int dim, int n);

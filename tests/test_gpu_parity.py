@@ -127,6 +127,24 @@ def test_explicit_dirs_weights_and_call_weights(gpu_lib):
     assert np.array_equal(q3, q)
 
 
+def test_n32_large_batch_job_tables(gpu_lib):
+    """2D n = 32 batches that fill two rounds of the persistent grid take the
+    per-job tables (one wave per SIMD fewer than the shared rows): 16384 cells
+    tiling 64 distinct draws, every distinct cell against the oracle, and the
+    tiles identical (the same cell gives the same bits in every slot)."""
+    distinct, B = 64, 16384
+    base = workloads.random_positive(32032, 2, 32, distinct)
+    f = np.ascontiguousarray(np.tile(base.reshape(distinct, -1), (B // distinct, 1)))
+    for P in (8, 16):
+        plan = gpu_lib.Plan(2, 32, 8.0, num_dirs=P)
+        q = _eval(plan, f).reshape(B, -1)
+        errs = per_cell_rel_linf(q[:distinct], oracle_q(plan, base), 32 * 32)
+        print("n=32 P=%d batch %d: max cell rel err %.3e" % (P, B, errs.max()))
+        assert errs.max() <= TOL
+        assert np.array_equal(q[:distinct], q[B - distinct:])
+        plan.close()
+
+
 def test_n64_job_tables_signed_and_zero_weights(gpu_lib):
     """2D n = 64 plain plans fold each job's weight into its multiplier tables
     (sgn(W) sqrt|W| on one row, sqrt|W| on the other).  Explicit lines with an
