@@ -212,11 +212,13 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
             e = variant ? shaped_grid(k_eval2d<N, 1, true>, 256, li.lds, items, lim, li.grid)
                         : shaped_grid(k_eval2d<N, 0, true>, 256, li.lds, items, lim, li.grid);
         else {
-            // n = 64 and 32: per-job tables when they fit in LDS and either keep the
-            // occupancy of the shared rows (n = 64) or the batch fills at least two
-            // rounds of the persistent grid (n = 32: the tables cost registers, one
-            // wave per SIMD fewer, which measured slower at 4096 cells, 0.047 against
-            // 0.042 ms, and faster at 32768, 0.278 against 0.297 ms)
+            // n = 64 and 32: per-job tables when they fit in LDS and keep the
+            // occupancy of the shared rows, or (n = 32) cost at most one wave of four
+            // per SIMD and the batch fills at least two rounds of the persistent grid
+            // (the tables cost registers at n = 32: measured slower at 4096 cells,
+            // 0.047 against 0.042 ms, and faster at 32768, 0.278 against 0.297 ms; at
+            // n = 64 a plan whose tables halve the occupancy, as with 16 or more jobs,
+            // runs 1.5x slower with them)
             if constexpr (N == 64 || N == 32) {
                 const size_t lds_jt = lds2d_jobs<N>(pl.jt_floats);
                 if (lim.allow_jt && lds_jt <= kMaxLds) {
@@ -227,7 +229,7 @@ hipError_t eval2d_info(const DevPlan& pl, int batch, int variant, LaunchInfo& li
                     li.jt = (variant ? occupancy_grid(k_eval2d<N, 1, false, true>, 256, lds_jt, 1 << 30, full_jt)
                                      : occupancy_grid(k_eval2d<N, 0, false, true>, 256, lds_jt, 1 << 30,
                                                       full_jt)) == hipSuccess &&
-                            (full_jt >= full || items >= 2 * full_jt);
+                            (full_jt >= full || (N == 32 && items >= 2 * full_jt && 4 * full_jt >= 3 * full));
                     if (li.jt) li.lds = lds_jt;
                 }
             }
