@@ -14,11 +14,51 @@ namespace qdvm {
 //   Y: pencil pi = x*n + z, e = y
 //   Z: pencil pi = x*n + y, e = z      (spectral; scratch/tables at Kz*n^2 + pi)
 // LDS address of (x, y, z): x*SX + y*(n+1) + z, SX = n*(n+1).
-template <int N, int PH>
+// n = 32 with one pencil per thread (1024 threads): in phases Y and Z a wave
+// holds two x-slabs, and they are chosen as a slab and its mirror (x and -x;
+// wave 0: the self-mirror slabs 0 and n/2), so that the spectral pencils
+// (Kx, Ky) and (-Kx, -Ky) sit in one wave and the half-stored spectrum's mirror
+// half can come by cross-lane shuffle.  Elsewhere slab s of phases Y and Z is
+// x = s.
+template <int N, int T>
+constexpr bool mirror_slabs() { return N == 32 && T == N * N; }
+
+template <int N, int T>
+__device__ __forceinline__ int slab_x(int s)
+{
+    if constexpr (mirror_slabs<N, T>()) {
+        const int w = s >> 1, h = s & 1;
+        return h == 0 ? w : (w == 0 ? N / 2 : N - w);
+    } else {
+        return s;
+    }
+}
+
+// Logical spectral pencil Kx n + Ky of the thread pencil pi (phase Z).
+template <int N, int T>
+__device__ __forceinline__ int spec_pi(int pi)
+{
+    return slab_x<N, T>(pi / N) * N + pi % N;
+}
+
+// Thread pencil that holds the mirror (-Kx, -Ky) of thread pencil pi.
+template <int N, int T>
+__device__ __forceinline__ int mirror_thread(int pi)
+{
+    if constexpr (mirror_slabs<N, T>()) {
+        const int s = pi / N, w = s >> 1, h = s & 1;
+        return (2 * w + (w == 0 ? h : 1 - h)) * N + (N - pi % N) % N;
+    } else {
+        const int kx = pi / N, ky = pi % N;
+        return ((N - kx) % N) * N + (N - ky) % N;
+    }
+}
+
+template <int N, int PH, int T = 0>
 __device__ __forceinline__ int addr3(int pi, int e)
 {
     constexpr int SY = N + 1, SX = N * (N + 1);
-    const int a = pi / N, b = pi % N;
+    const int a = PH == 0 ? pi / N : slab_x<N, T>(pi / N), b = pi % N;
     if (PH == 0) return e * SX + a * SY + b;
     if (PH == 1) return a * SX + e * SY + b;
     return a * SX + b * SY + e;
@@ -36,13 +76,13 @@ __device__ __forceinline__ void block_transpose(float2 (&z)[Q][N], float* xb, in
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int e = 0; e < N; ++e) xb[addr3<N, PA>(tid + q * T, e)] = part ? z[q][e].y : z[q][e].x;
+            for (int e = 0; e < N; ++e) xb[addr3<N, PA, T>(tid + q * T, e)] = part ? z[q][e].y : z[q][e].x;
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int e = 0; e < N; ++e) {
-                const float v = xb[addr3<N, PB>(tid + q * T, e)];
+                const float v = xb[addr3<N, PB, T>(tid + q * T, e)];
                 if (part) z[q][e].y = v;
                 else z[q][e].x = v;
             }
@@ -65,13 +105,13 @@ __device__ __forceinline__ void wave_transpose(float2 (&z)[Q][N], float* xb, int
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int e = 0; e < N; ++e) xb[addr3<N, PA>(tid + q * T, e)] = part ? z[q][e].y : z[q][e].x;
+            for (int e = 0; e < N; ++e) xb[addr3<N, PA, T>(tid + q * T, e)] = part ? z[q][e].y : z[q][e].x;
         wave_sync();
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int e = 0; e < N; ++e) {
-                const float v = xb[addr3<N, PB>(tid + q * T, e)];
+                const float v = xb[addr3<N, PB, T>(tid + q * T, e)];
                 if (part) z[q][e].y = v;
                 else z[q][e].x = v;
             }
@@ -189,9 +229,54 @@ __device__ __forceinline__ void job3d_multiply(float2 (&z)[Q][N], rsrc_t rs, con
 {
     constexpr int NN = N * N, RS = NN * 4;
     const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+    if constexpr (mirror_slabs<N, T>()) {
+        // elements k and n - k together: the lane reads its own half pencil of the
+        // spectrum and of the plane table; element n - k of its pencil is the
+        // conjugate (for the even plane table: the value) of element k of the
+        // mirror pencil (-Kx, -Ky), which a lane of the same wave has just read,
+        // so it comes by shuffle.  The line multiplier walks forward for k and
+        // backward (from k = n - 1) for n - k.
+        const int pi = spec_pi<N, T>(tid), kx = pi / N, ky = pi % N;
+        const int mlane = mirror_thread<N, T>(tid) & 63;
+        const HalfSpec<N, N * N * 8> hs = half3d<N>(rs, pi);
+        RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
+        RowWalk<N> am(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky - J.e[2]), modc<N>(-J.e[2]));
+        constexpr int H = N / 2 + 1, CH = 4;
+#pragma unroll
+        for (int k0 = 0; k0 < H; k0 += CH) {
+            float2 F[CH];
+            float a2[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+                if (k0 + i < H) {
+                    F[i] = hs.get(k0 + i);
+                    a2[i] = bload(rap, pi * 4, (k0 + i) * RS);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int k = k0 + i;
+                if (k >= H) break;
+                const float al = a.get();
+                z[0][k] = make_float2(__builtin_fmaf(al, F[i].x, -a2[i] * F[i].y),
+                                      __builtin_fmaf(al, F[i].y, a2[i] * F[i].x));
+                a.next();
+                if (k >= 1 && k < N / 2) {
+                    const float2 Fm = make_float2(__shfl(F[i].x, mlane, 64), -__shfl(F[i].y, mlane, 64));
+                    const float a2m = __shfl(a2[i], mlane, 64);
+                    const float bl = am.get();
+                    z[0][N - k] = make_float2(__builtin_fmaf(bl, Fm.x, -a2m * Fm.y),
+                                              __builtin_fmaf(bl, Fm.y, a2m * Fm.x));
+                    am.next();
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+        const int pi = spec_pi<N, T>(tid + q * T), kx = pi / N, ky = pi % N;
         const HalfSpec<N, N * N * 8> hs = half3d<N>(rs, pi);
         RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
         if constexpr (C <= 4) {
@@ -249,14 +334,14 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
     float acc[Q][NR > 0 ? NR : 1];
     auto lslot = [&](int q, int x) -> float& { return lacc[(x - NR) * (T * Q) + tid + q * T]; };
 #pragma unroll
-    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
+    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, spec_pi<N, T>(tid + q * T)).put(z[q]);
     if (loss) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int k0 = 0; k0 < N; k0 += 8) {
                 float l[8];
-                load_run<8>(l, rlam, (tid + q * T) * 4, k0, RS);
+                load_run<8>(l, rlam, spec_pi<N, T>(tid + q * T) * 4, k0, RS);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     z[q][k0 + k].x *= l[k];
@@ -333,7 +418,7 @@ __device__ __forceinline__ void job3d_multiply_bilinear(float2 (&z)[Q][N], rsrc_
     const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+        const int pi = spec_pi<N, T>(tid + q * T), kx = pi / N, ky = pi % N;
         const HalfSpec<N, N * N * 8> gs = half3d<N>(rgs, pi);
         const HalfSpec<N, N * N * 8> fs = half3d<N>(rfs, pi);
         RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
@@ -378,14 +463,14 @@ __device__ __forceinline__ void cell3d_eval_bilinear(const DevPlan& pl, const Ce
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(rg, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) half3d<N>(rgh, tid + q * T).put(z[q]);
+    for (int q = 0; q < Q; ++q) half3d<N>(rgh, spec_pi<N, T>(tid + q * T)).put(z[q]);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
+    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, spec_pi<N, T>(tid + q * T)).put(z[q]);
     float acc[Q][NR > 0 ? NR : 1];
     auto lslot = [&](int q, int x) -> float& { return lacc[(x - NR) * (T * Q) + tid + q * T]; };
 #pragma unroll
@@ -393,7 +478,7 @@ __device__ __forceinline__ void cell3d_eval_bilinear(const DevPlan& pl, const Ce
 #pragma unroll
         for (int k0 = 0; k0 < N; k0 += 8) {
             float l[8];
-            load_run<8>(l, rlam, (tid + q * T) * 4, k0, RS);
+            load_run<8>(l, rlam, spec_pi<N, T>(tid + q * T) * 4, k0, RS);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 z[q][k0 + k].x *= l[k];
@@ -541,13 +626,13 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
         }
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) half3d<N>(rgh, tid + q * T).put(z[q]);
+    for (int q = 0; q < Q; ++q) half3d<N>(rgh, spec_pi<N, T>(tid + q * T)).put(z[q]);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int k0 = 0; k0 < N; k0 += 8) {
             float l[8];
-            load_run<8>(l, rlam, (tid + q * T) * 4, k0, RS);
+            load_run<8>(l, rlam, spec_pi<N, T>(tid + q * T) * 4, k0, RS);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 z[q][k0 + k].x *= l[k];
@@ -566,13 +651,13 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
+    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, spec_pi<N, T>(tid + q * T)).put(z[q]);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int k0 = 0; k0 < N; k0 += 8) {
             float l[8];
-            load_run<8>(l, rlam, (tid + q * T) * 4, k0, RS);
+            load_run<8>(l, rlam, spec_pi<N, T>(tid + q * T) * 4, k0, RS);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 z[q][k0 + k].x *= l[k];
@@ -668,8 +753,7 @@ __device__ __forceinline__ void mirror_exchange(const float2 (&z)[Q][N], float2 
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
-            const int mi = ((N - kx) % N) * N + (N - ky) % N;
+            const int mi = mirror_thread<N, T>(tid + q * T);
 #pragma unroll
             for (int r = 0; r <= N / 2; ++r) {
                 const float v = xb[r * NN + mi];
@@ -707,7 +791,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         for (int x = 0; x < N; ++x) z[q][x] = make_float2(bload(cl.f, (tid + q * T) * 4, x * RS), 0.f);
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, tid + q * T).put(z[q]);
+    for (int q = 0; q < Q; ++q) half3d<N>(cl.fh, spec_pi<N, T>(tid + q * T)).put(z[q]);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -719,7 +803,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
     fwd3d<N, T, Q, RV>(z, xb, tid);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int pi = tid + q * T;
+        const int pi = spec_pi<N, T>(tid + q * T);
         const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi);
         // own half of the pencil, written by this lane; each chunk's reads are
         // issued before its stores (which the compiler cannot tell apart from them)
@@ -742,7 +826,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const int pi = tid + q * T;
+                const int pi = spec_pi<N, T>(tid + q * T);
                 const float2 F = half3d<N>(cl.fh, pi).get(k);
                 const float l = bload(rlam, pi * 4, k * RS);
                 z[q][k] = make_float2(l * (F.x - z[q][k].y), l * (F.y + z[q][k].x));
@@ -774,7 +858,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int k = 0; k <= N / 2; ++k) bstore2(make_float2(0.f, 0.f), rsh, (tid + q * T) * 8, k * RS2);
+        for (int k = 0; k <= N / 2; ++k) bstore2(make_float2(0.f, 0.f), rsh, spec_pi<N, T>(tid + q * T) * 8, k * RS2);
     // the jobs read mirrored pencils of the spectrum and of R, written by other threads
     __syncthreads();
 
@@ -786,7 +870,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         float spart = 0.f;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int pi = tid + q * T, kx = pi / N, ky = pi % N;
+            const int pi = spec_pi<N, T>(tid + q * T), kx = pi / N, ky = pi % N;
             const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi);
             const int rown = pi * 4, rmir = fh.mir / 2;
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
@@ -826,7 +910,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         for (int q = 0; q < Q; ++q) {
             // the multipliers are read again rather than kept from the first
             // multiply: holding them through two transforms would spill
-            const int pi = reread(tid + q * T), kx = pi / N, ky = pi % N;
+            const int pi = spec_pi<N, T>(reread(tid + q * T)), kx = pi / N, ky = pi % N;
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
 #pragma unroll
             for (int k0 = 0; k0 <= N / 2; k0 += 4) {
@@ -863,7 +947,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const HalfSpec<N, N * N * 8> sh = half3d<N>(rsh, tid + q * T);
+            const HalfSpec<N, N * N * 8> sh = half3d<N>(rsh, spec_pi<N, T>(tid + q * T));
 #pragma unroll
             for (int k = 0; k < N; ++k) z[q][k] = sh.get(k);
         }
