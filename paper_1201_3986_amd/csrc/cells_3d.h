@@ -416,6 +416,50 @@ __device__ __forceinline__ void job3d_multiply_bilinear(float2 (&z)[Q][N], rsrc_
 {
     constexpr int NN = N * N, RS = NN * 4;
     const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
+    if constexpr (mirror_slabs<N, T>()) {
+        // elements k and n - k together, the mirror halves of both spectra and of
+        // the plane table by shuffle (as in job3d_multiply)
+        const int pi = spec_pi<N, T>(tid), kx = pi / N, ky = pi % N;
+        const int mlane = mirror_thread<N, T>(tid) & 63;
+        const HalfSpec<N, N * N * 8> gs = half3d<N>(rgs, pi);
+        const HalfSpec<N, N * N * 8> fs = half3d<N>(rfs, pi);
+        RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
+        RowWalk<N> am(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky - J.e[2]), modc<N>(-J.e[2]));
+        constexpr int H = N / 2 + 1;
+#pragma unroll
+        for (int k0 = 0; k0 < H; k0 += C) {
+            float2 G[C], F[C];
+            float a2[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                if (k0 + i < H) {
+                    G[i] = gs.get(k0 + i);
+                    F[i] = fs.get(k0 + i);
+                    a2[i] = bload(rap, pi * 4, (k0 + i) * RS);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const int k = k0 + i;
+                if (k >= H) break;
+                const float al = a.get();
+                z[0][k] = make_float2(__builtin_fmaf(al, G[i].x, -a2[i] * F[i].y),
+                                      __builtin_fmaf(al, G[i].y, a2[i] * F[i].x));
+                a.next();
+                if (k >= 1 && k < N / 2) {
+                    const float2 Gm = make_float2(__shfl(G[i].x, mlane, 64), -__shfl(G[i].y, mlane, 64));
+                    const float2 Fm = make_float2(__shfl(F[i].x, mlane, 64), -__shfl(F[i].y, mlane, 64));
+                    const float a2m = __shfl(a2[i], mlane, 64);
+                    const float bl = am.get();
+                    z[0][N - k] = make_float2(__builtin_fmaf(bl, Gm.x, -a2m * Fm.y),
+                                              __builtin_fmaf(bl, Gm.y, a2m * Fm.x));
+                    am.next();
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int pi = spec_pi<N, T>(tid + q * T), kx = pi / N, ky = pi % N;
@@ -740,6 +784,16 @@ __device__ __forceinline__ void mirror_exchange(const float2 (&z)[Q][N], float2 
                                                 int tid)
 {
     constexpr int NN = N * N;
+    if constexpr (mirror_slabs<N, T>()) {
+        // the mirror pencil is in the same wave: shuffles, no LDS round trip
+        const int mlane = mirror_thread<N, T>(tid) & 63;
+#pragma unroll
+        for (int r = 0; r <= N / 2; ++r) {
+            const float2 v = z[0][(N - r) % N];
+            um[0][r] = make_float2(__shfl(v.x, mlane, 64), __shfl(v.y, mlane, 64));
+        }
+        return;
+    }
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
         __syncthreads();
@@ -868,8 +922,51 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
         const float cw = gload(jobw, jb);
         const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
         float spart = 0.f;
+        if constexpr (mirror_slabs<N, T>()) {
+            // elements k and n - k together: the mirror halves of the spectrum, of R
+            // (even) and of the plane table (even) by shuffle (as in job3d_multiply)
+            const int pi = spec_pi<N, T>(tid), kx = pi / N, ky = pi % N;
+            const int mlane = mirror_thread<N, T>(tid) & 63;
+            const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi);
+            RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky), modc<N>(J.e[2]));
+            RowWalk<N> am(atab + J.M * N, modc<N>(J.e[0] * kx + J.e[1] * ky - J.e[2]), modc<N>(-J.e[2]));
+            constexpr int H = N / 2 + 1, CH = 4;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+            for (int k0 = 0; k0 < H; k0 += CH) {
+                float2 F[CH];
+                float R[CH], a2[CH];
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    if (k0 + i < H) {
+                        F[i] = fh.get(k0 + i);
+                        R[i] = bload(rr, pi * 4, (k0 + i) * RS);
+                        a2[i] = bload(rap, pi * 4, (k0 + i) * RS);
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const int k = k0 + i;
+                    if (k >= H) break;
+                    const float al = a.get();
+                    z[0][k] = make_float2(__builtin_fmaf(al, F[i].x, -a2[i] * F[i].y),
+                                          __builtin_fmaf(al, F[i].y, a2[i] * F[i].x));
+                    spart = __builtin_fmaf(al * a2[i], R[i], spart);
+                    a.next();
+                    if (k >= 1 && k < N / 2) {
+                        const float2 Fm = make_float2(__shfl(F[i].x, mlane, 64), -__shfl(F[i].y, mlane, 64));
+                        const float Rm = __shfl(R[i], mlane, 64), a2m = __shfl(a2[i], mlane, 64);
+                        const float bl = am.get();
+                        z[0][N - k] = make_float2(__builtin_fmaf(bl, Fm.x, -a2m * Fm.y),
+                                                  __builtin_fmaf(bl, Fm.y, a2m * Fm.x));
+                        spart = __builtin_fmaf(bl * a2m, Rm, spart);
+                        am.next();
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < (mirror_slabs<N, T>() ? 0 : Q); ++q) {
             const int pi = spec_pi<N, T>(tid + q * T), kx = pi / N, ky = pi % N;
             const HalfSpec<N, N * N * 8> fh = half3d<N>(cl.fh, pi);
             const int rown = pi * 4, rmir = fh.mir / 2;
