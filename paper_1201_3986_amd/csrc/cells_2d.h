@@ -891,17 +891,18 @@ __device__ __forceinline__ void cell2d_eval_split_pair(const DevPlan& pl, const 
 // Adjoint of one 2D cell; the algebra is written out above cell3d_vjp (R, the
 // Hermitian accumulator S).  The mirror row -K0 of the lane's row K0 = j is
 // another lane of the same wave: uhat(-K) comes by shuffle.  rr: the table R
-// (half rows, 4 bytes per element) in the second spectral slot.
+// (half rows, 4 bytes per element) in the second spectral slot; rnone: a
+// descriptor of the accumulator's base with extent 0.
 template <int N, int RV>
 __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, rsrc_t rc, rsrc_t rr,
-                                           rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
+                                           rsrc_t rsh, rsrc_t rnone, rsrc_t rlam, const float* __restrict__ jobw,
                                            double* __restrict__ gwp, bool gw_first, bool valid, float inv_n2,
                                            float inv_n, float* xb, const float* dtab, int j)
 {
     constexpr int RS = N * 4, RS2 = N * 8;
     const int mrow = (N - j) & (N - 1);                          // mirror row
     const int mlane = (int)(threadIdx.x & 63) - j + mrow;        // its lane in the wave
-    const int rown = it.vspec / 2, rmir = rown + (mrow - j) * 4; // R: own and mirror row offsets
+    const int rown = it.vspec / 2;                               // R: own row offset
     float2 z[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) z[i] = make_float2(bload(it.f, it.vcell, i * RS), 0.f);
@@ -946,14 +947,18 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
         for (int i = 0; i < N; ++i) bstore(-cv[i] * z[i].x - z[i].y, it.q, it.vcell, i * RS);
     }
 
-    // the accumulator starts at zero (an unconditional read-modify-write in the
-    // job loop keeps that loop free of per-element branches)
-#pragma unroll
-    for (int k = 0; k <= N / 2; ++k) bstore2(make_float2(0.f, 0.f), rsh, it.vspec, k * RS2);
+    // The accumulator S lives in memory between jobs, in half rows.  The first
+    // job reads it through an empty descriptor (the hardware returns 0 for every
+    // read and drops every write, with no memory request), so it needs no zero
+    // fill; the last job keeps its sums in z, the final transform's input, and
+    // writes through the empty descriptor instead of storing them to be read
+    // back.
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
+        const rsrc_t rsr = jb == 0 ? rnone : rsh;
+        const rsrc_t rsw = jb + 1 == pl.njobs ? rnone : rsh;
         float spart = 0.f;
         {
             // elements k and n - k together: the lane reads its own half row (k <= n/2)
@@ -1031,7 +1036,7 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
 #pragma unroll
                 for (int i = 0; i < C; ++i)
                     if (k0 + i <= N / 2) {
-                        sv[i] = bload2(rsh, it.vspec, (k0 + i) * RS2);
+                        sv[i] = bload2(rsr, it.vspec, (k0 + i) * RS2);
                         w[i] = make_float2(a.get(), b.get());
                         a.next();
                         b.next();
@@ -1053,16 +1058,22 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
                     const float al = 0.5f * cw * w[i].x, ap = 0.5f * cw * w[i].y;
                     float2 t = make_float2(__builtin_fmaf(al, z[k].x + mx, ap * (z[k].y + my)),
                                            __builtin_fmaf(al, z[k].y - my, -ap * (z[k].x - mx)));
-                    bstore2(make_float2(t.x + sv[i].x, t.y + sv[i].y), rsh, it.vspec, k * RS2);
+                    // z[k] is not read again in this job: element k is the
+                    // mirror of n - k > n/2 (never formed here) except for k = 0
+                    // and n/2, whose mirror reads precede this write
+                    z[k] = make_float2(t.x + sv[i].x, t.y + sv[i].y);
+                    bstore2(z[k], rsw, it.vspec, k * RS2);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
     if (pl.njobs > 0) {
-        const HalfSpec<N, N * 8> sh = half2d<N>(rsh, it.vspec, j);
+        // z[0..n/2] holds the own half row of S; element k > n/2 is the conjugate
+        // of element n - k of the mirror row
 #pragma unroll
-        for (int k = 0; k < N; ++k) z[k] = sh.get(k);
+        for (int k = N / 2 + 1; k < N; ++k)
+            z[k] = make_float2(__shfl(z[N - k].x, mlane, 64), -__shfl(z[N - k].y, mlane, 64));
         inv2d<N, RV>(z, xb, j);
         {
             float gv[N];

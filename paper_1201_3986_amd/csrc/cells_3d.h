@@ -829,10 +829,11 @@ __device__ __forceinline__ void mirror_exchange(const float2 (&z)[Q][N], float2 
 // which uses A(c h) + B(c g) = Re IFFT((a - i a') F(c h + i c g)), valid because
 // the multipliers a = alpha_j and a' = alpha'_j are real and even.
 // Jobs jb0, jb0 + jstep, ...; the loss part only if `loss` (see cell3d_eval).
-// rr: R of the cell (half pencils, 4 bytes per element).
+// rr: R of the cell (half pencils, 4 bytes per element); rnone: a descriptor of
+// the accumulator's base with extent 0.
 template <int N, int T, int RV>
 __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, rsrc_t rc, rsrc_t rr,
-                                           rsrc_t rsh, rsrc_t rlam, const float* __restrict__ jobw,
+                                           rsrc_t rsh, rsrc_t rnone, rsrc_t rlam, const float* __restrict__ jobw,
                                            double* __restrict__ gwp, bool gw_first, float inv_n2, float inv_n,
                                            float* xb, float* red, const float* dtab, int tid, int jb0 = 0,
                                            int jstep = 1, bool loss = true)
@@ -907,19 +908,22 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
             for (int k = 0; k < N; ++k) bstore(0.f, cl.q, (tid + q * T) * 4, k * RS);
     }
-    // the accumulator starts at zero (an unconditional read-modify-write in the
-    // job loop keeps that loop free of per-element branches)
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int k = 0; k <= N / 2; ++k) bstore2(make_float2(0.f, 0.f), rsh, spec_pi<N, T>(tid + q * T) * 8, k * RS2);
     // the jobs read mirrored pencils of the spectrum and of R, written by other threads
     __syncthreads();
 
+    // The accumulator S lives in memory between jobs, in half pencils.  The
+    // first job reads it through an empty descriptor (every read returns 0 and
+    // every write is dropped, with no memory request), so it needs no zero fill.
+    // When the mirror pencil is in the same wave the last job keeps its sums in
+    // z, the final transform's input, and writes through the empty descriptor
+    // instead of storing them to be read back.
+    constexpr bool keep_last = mirror_slabs<N, T>();
     const float* atab = dtab_alpha(dtab, pl);
     for (int jb = jb0; jb < pl.njobs; jb += jstep) {
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
+        const rsrc_t rsr = jb == jb0 ? rnone : rsh;
+        const rsrc_t rsw = keep_last && jb + jstep >= pl.njobs ? rnone : rsh;
         const rsrc_t rap = make_rsrc(pl.aperp + (size_t)jb * NN * N, NN * N * 4);
         float spart = 0.f;
         if constexpr (mirror_slabs<N, T>()) {
@@ -1018,7 +1022,7 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     if (k0 + i <= N / 2) {
-                        sv[i] = bload2(rsh, pi * 8, (k0 + i) * RS2);
+                        sv[i] = bload2(rsr, pi * 8, (k0 + i) * RS2);
                         a2[i] = 0.5f * cw * bload(rap, pi * 4, (k0 + i) * RS);
                         a1[i] = 0.5f * cw * a.get();
                         a.next();
@@ -1033,20 +1037,31 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
                     const float2 u = z[q][k], m = um[q][k];
                     float2 t = make_float2(__builtin_fmaf(al, u.x + m.x, a2[i] * (u.y + m.y)),
                                            __builtin_fmaf(al, u.y - m.y, -a2[i] * (u.x - m.x)));
-                    bstore2(make_float2(t.x + sv[i].x, t.y + sv[i].y), rsh, pi * 8, k * RS2);
+                    const float2 sum = make_float2(t.x + sv[i].x, t.y + sv[i].y);
+                    if constexpr (keep_last) z[q][k] = sum;   // u = z[q][k] is not read again in this job
+                    bstore2(sum, rsw, pi * 8, k * RS2);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
     if (jb0 < pl.njobs) {
-        // the other half of each pencil is the mirror lane's
-        __syncthreads();
+        if constexpr (keep_last) {
+            // z[0][0..n/2] holds the own half pencil of S; element k > n/2 is the
+            // conjugate of element n - k of the mirror pencil (-Kx, -Ky)
+            const int mlane = mirror_thread<N, T>(tid) & 63;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const HalfSpec<N, N * N * 8> sh = half3d<N>(rsh, spec_pi<N, T>(tid + q * T));
+            for (int k = N / 2 + 1; k < N; ++k)
+                z[0][k] = make_float2(__shfl(z[0][N - k].x, mlane, 64), -__shfl(z[0][N - k].y, mlane, 64));
+        } else {
+            // the other half of each pencil is the mirror lane's
+            __syncthreads();
 #pragma unroll
-            for (int k = 0; k < N; ++k) z[q][k] = sh.get(k);
+            for (int q = 0; q < Q; ++q) {
+                const HalfSpec<N, N * N * 8> sh = half3d<N>(rsh, spec_pi<N, T>(tid + q * T));
+#pragma unroll
+                for (int k = 0; k < N; ++k) z[q][k] = sh.get(k);
+            }
         }
         inv3d<N, T, Q, RV>(z, xb, tid);
         constexpr int C = N % 8 == 0 ? 8 : N;

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const floa
     const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
     const rsrc_t rr = make_rsrc(s.spec2 + sbase, CPB * NPTS * 8);
     const rsrc_t rsh = make_rsrc(s.acc + sbase, CPB * NPTS * 8);
+    const rsrc_t rnone = make_rsrc(s.acc + sbase, 0);
     Item2D it;
     it.fh = make_rsrc(s.spec + sbase, CPB * NPTS * 8);
     it.vcell = (local * NPTS + j) * 4;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(256) void k_vjp2d(DevPlan pl, int batch, const floa
         it.q = make_rsrc(g + (size_t)first * NPTS, nvalid * NPTS * 4);
         const rsrc_t rc = make_rsrc(c + (size_t)first * NPTS, nvalid * NPTS * 4);
         // grad_w partials: row blockIdx * CPB + local accumulates this slot's cells
-        cell2d_vjp<N, RV>(pl, it, rc, rr, rsh, rlam, s.jobw,
+        cell2d_vjp<N, RV>(pl, it, rc, rr, rsh, rnone, rlam, s.jobw,
                           s.gw_part + ((size_t)blockIdx.x * CPB + local) * pl.njobs, item == (int)blockIdx.x,
                           valid, inv_n2, inv_n, xb, dtab, j);
     }

@@ -97,7 +97,8 @@ __global__ __launch_bounds__(T) void k_vjp3d(DevPlan pl, int batch, const float*
         cl.q = make_rsrc(g + (size_t)cell * NPTS, NPTS * 4);
         const rsrc_t rc = make_rsrc(c + (size_t)cell * NPTS, NPTS * 4);
         // grad_w partials: row blockIdx accumulates this workgroup's cells
-        cell3d_vjp<N, T, RV>(pl, cl, rc, rr, rsh, rlam, s.jobw, s.gw_part + (size_t)blockIdx.x * pl.njobs,
+        cell3d_vjp<N, T, RV>(pl, cl, rc, rr, rsh, make_rsrc(s.acc + slot, 0), rlam, s.jobw,
+                             s.gw_part + (size_t)blockIdx.x * pl.njobs,
                              cell == (int)blockIdx.x, inv_n2, inv_n, xb, red, dtab, tid);
     }
 }
@@ -173,7 +174,8 @@ __global__ __launch_bounds__(T) void k_vjp3d_js(DevPlan pl, int batch, int G, co
     cl.q = make_rsrc(s.part + ((size_t)g * batch + cell) * NPTS, NPTS * 4);
     cl.fh = make_rsrc(s.spec + slot, NPTS * 8);
     cell3d_vjp<N, T, RV>(pl, cl, make_rsrc(c + (size_t)cell * NPTS, NPTS * 4), make_rsrc(s.spec2 + slot, NPTS * 8),
-                         make_rsrc(s.acc + slot, NPTS * 8), make_rsrc(s.lam, NPTS * 4), s.jobw,
+                         make_rsrc(s.acc + slot, NPTS * 8), make_rsrc(s.acc + slot, 0), make_rsrc(s.lam, NPTS * 4),
+                         s.jobw,
                          s.gw_part + (size_t)cell * pl.njobs, true, inv_n * inv_n, inv_n, xb, red, dtab, tid, g,
                          G, g == 0);
 }
