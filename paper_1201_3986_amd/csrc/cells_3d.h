@@ -409,9 +409,8 @@ __device__ __forceinline__ void cell3d_eval(const DevPlan& pl, const Cell3D& cl,
 
 // z = alpha ghat + i alpha' fhat for one direction of the bilinear operator
 // (spectral layout as job3d_multiply; chunks of C elements, each chunk's reads
-// issued before their use).  MDIFF: z = alpha (fhat - ghat) + i alpha' ghat
-// instead, the transform whose product is line(f - g) plane(g).
-template <int N, int T, int Q, int C, bool MDIFF = false>
+// issued before their use).
+template <int N, int T, int Q, int C>
 __device__ __forceinline__ void job3d_multiply_bilinear(float2 (&z)[Q][N], rsrc_t rgs, rsrc_t rfs, const DevPlan& pl,
                                                         const JobDesc& J, int jb, const float* atab, int tid)
 {
@@ -439,14 +438,6 @@ __device__ __forceinline__ void job3d_multiply_bilinear(float2 (&z)[Q][N], rsrc_
                     a2[i] = bload(rap, pi * 4, (k0 + i) * RS);
                 }
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (MDIFF) {
-#pragma unroll
-                for (int i = 0; i < C; ++i) {
-                    const float2 g = G[i];
-                    G[i] = csub(F[i], g);
-                    F[i] = g;
-                }
-            }
 #pragma unroll
             for (int i = 0; i < C; ++i) {
                 const int k = k0 + i;
@@ -486,14 +477,6 @@ __device__ __forceinline__ void job3d_multiply_bilinear(float2 (&z)[Q][N], rsrc_
                 a2[i] = bload(rap, pi * 4, (k0 + i) * RS);
             }
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (MDIFF) {
-#pragma unroll
-                for (int i = 0; i < C; ++i) {
-                    const float2 g = G[i];
-                    G[i] = csub(F[i], g);
-                    F[i] = g;
-                }
-            }
 #pragma unroll
             for (int i = 0; i < C; ++i) {
                 const float al = a.get();
@@ -620,18 +603,11 @@ __device__ __forceinline__ void block_sum5d(double (&v)[5], double* red, int tid
     }
 }
 
-// How the near-equilibrium evaluation holds the transforms of g and f of a
-// direction: both in registers; that of g parked in memory (rtg) while that of
-// f is formed; or as two bilinear transforms (line(g) + i plane(f), then
-// line(M) + i plane(g)) whose products are taken as soon as each is formed.
-enum SplitHold { kHoldRegs = 0, kHoldStage = 1, kHoldPairs = 2 };
-
 // Near-equilibrium evaluation of one 3D cell: Q(f, f) - Q(M, M) through
 // Q(g, f) + Q(M, g), g = f - M, M the Maxwellian of the cell's moments (the
-// transform layout and the error argument are those of cell2d_eval_split).
-// LACC: with kHoldPairs, gain elements per lane kept in LDS over the direction
-// loop (the LDS of red and of the Maxwellian factors, no longer read by then).
-template <int N, int T, int RV, int HOLD, int LACC = 0>
+// transform layout, the error argument and STAGE are those of
+// cell2d_eval_split).
+template <int N, int T, int RV, bool STAGE>
 __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3D& cl, rsrc_t rgh, rsrc_t rtg,
                                                   rsrc_t rlam, const float* __restrict__ jobw, float dt, float* xb,
                                                   double* red, const float* dtab, int tid)
@@ -755,53 +731,13 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
     }
 
     const float* atab = dtab_alpha(dtab, pl);
-    if constexpr (HOLD == kHoldPairs) {
-        // gain = line(g) plane(f) + line(M) plane(g): IFFT(alpha ghat + i alpha' fhat),
-        // then IFFT(alpha Mhat + i alpha' ghat) with Mhat = fhat - ghat
-        constexpr int NR = N - LACC, CB = (N == 32 && Q == 1) ? 2 : 8;
-        float* lacc = (float*)red;
-        if constexpr (LACC > 0) {
-            __syncthreads();                     // every thread has read the Maxwellian factors
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-#pragma unroll
-                for (int x = NR; x < N; ++x) lacc[(x - NR) * (T * Q) + tid + q * T] = acc[q][x];
-        }
-        for (int jb = 0; jb < pl.njobs; ++jb) {
-            const JobDesc J = gload(pl.jobs, jb);
-            const float cw = gload(jobw, jb);
-#pragma nounroll
-            for (int t = 0; t < 2; ++t) {
-                if (t == 0) job3d_multiply_bilinear<N, T, Q, CB>(z, rgh, cl.fh, pl, J, jb, atab, tid);
-                else job3d_multiply_bilinear<N, T, Q, CB, true>(z, rgh, cl.fh, pl, J, jb, atab, tid);
-                inv3d<N, T, Q, RV>(z, xb, tid);
-#pragma unroll
-                for (int q = 0; q < Q; ++q)
-#pragma unroll
-                    for (int x = 0; x < N; ++x) {
-                        if (x < NR) {
-                            acc[q][x] = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, acc[q][x]);
-                        } else {
-                            float& l = lacc[(x - NR) * (T * Q) + tid + q * T];
-                            l = __builtin_fmaf(cw * z[q][x].x, z[q][x].y, l);
-                        }
-                    }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int x = NR; x < N; ++x) acc[q][x] = lacc[(x - NR) * (T * Q) + tid + q * T];
-        // the next cell's moment reduction writes this LDS again
-        if constexpr (LACC > 0) __syncthreads();
-    }
-    for (int jb = 0; jb < (HOLD == kHoldPairs ? 0 : pl.njobs); ++jb) {
+    for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
         float2 tg[Q][N];
         job3d_multiply<N, T, Q, (chunk3<N, Q>() == 4 ? 4 : 8)>(tg, rgh, pl, J, jb, atab, tid);
         inv3d<N, T, Q, RV>(tg, xb, tid);         // line(g) + i plane(g)
-        if constexpr (HOLD == kHoldStage) {
+        if constexpr (STAGE) {
 #pragma unroll
             for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -815,9 +751,8 @@ __device__ __forceinline__ void cell3d_eval_split(const DevPlan& pl, const Cell3
             for (int x0 = 0; x0 < N; x0 += 8) {
                 float2 t[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    t[i] = HOLD == kHoldStage ? bload2(rtg, (tid + q * T) * 8, (x0 + i) * RS2) : tg[q][x0 + i];
-                if constexpr (HOLD == kHoldStage) __builtin_amdgcn_sched_barrier(0);
+                for (int i = 0; i < 8; ++i) t[i] = STAGE ? bload2(rtg, (tid + q * T) * 8, (x0 + i) * RS2) : tg[q][x0 + i];
+                if constexpr (STAGE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int x = x0 + i;

@@ -55,17 +55,16 @@ __global__ __launch_bounds__(T) void k_eval3d(DevPlan pl, int batch, const float
     const rsrc_t rlam = make_rsrc(s.lam, NPTS * 4);
     Cell3D cl;
     cl.fh = make_rsrc(s.spec + (size_t)blockIdx.x * NPTS, NPTS * 8);
-    // near-equilibrium mode: spectrum of g; at n = 32 the transforms of g and f of a
-    // direction do not fit in the registers of 1024 threads at once, and each
-    // direction goes through two bilinear transforms instead
-    constexpr int HOLD = N == 32 ? kHoldPairs : kHoldRegs;
+    // near-equilibrium mode: spectrum of g, and for n = 32 (two transforms do not fit in the
+    // registers of 1024 threads) a staging area for the transform of g of each job
+    constexpr bool STAGE = N == 32;
     const rsrc_t rgh = make_rsrc(SPLIT ? s.spec2 + (size_t)blockIdx.x * NPTS : s.spec, NPTS * 8);
+    const rsrc_t rtg = make_rsrc(SPLIT ? s.spec2 + (size_t)(gridDim.x + blockIdx.x) * NPTS : s.spec, NPTS * 8);
     for (int cell = blockIdx.x; cell < batch; cell += gridDim.x) {
         cl.f = make_rsrc(f + (size_t)cell * NPTS, NPTS * 4);
         cl.q = make_rsrc(q + (size_t)cell * NPTS, NPTS * 4);
         if constexpr (SPLIT)
-            cell3d_eval_split<N, T, RV, HOLD, lacc3d<N, T>()>(pl, cl, rgh, rgh, rlam, s.jobw, dt, xb, red, dtab,
-                                                              tid);
+            cell3d_eval_split<N, T, RV, STAGE>(pl, cl, rgh, rtg, rlam, s.jobw, dt, xb, red, dtab, tid);
         else
             cell3d_eval<N, T, RV, lacc3d<N, T>()>(pl, cl, rlam, s.jobw, dt, xb, dtab, tid, 0, 1, true,
                                                   dtab + dtab_floats(pl));

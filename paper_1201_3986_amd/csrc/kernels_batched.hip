@@ -91,9 +91,9 @@ __device__ __forceinline__ void batch_item_3d(const DevPlan& pl, const BatchItem
     cl.q = make_rsrc(q + off, NPTS * 4);
     cl.fh = make_rsrc(slot, NPTS * 8);
     const rsrc_t rlam = make_rsrc(pl.lam0, NPTS * 4);
-    constexpr int HOLD = N == 32 ? kHoldStage : kHoldRegs;
+    constexpr bool STAGE = N == 32;
     if (SPLIT && pl.mode)
-        cell3d_eval_split<N, T, 0, HOLD>(pl, cl, make_rsrc(slot + b.gslot, NPTS * 8),
+        cell3d_eval_split<N, T, 0, STAGE>(pl, cl, make_rsrc(slot + b.gslot, NPTS * 8),
                                           make_rsrc(slot + 2 * b.gslot, NPTS * 8), rlam, pl.jobw0, dt, xbase, red,
                                           dtab, threadIdx.x);
     else
