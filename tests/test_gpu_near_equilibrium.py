@@ -91,6 +91,21 @@ def test_all_sizes_against_definition(gpu_lib, d, n, P, cells):
     assert errs.max() <= TOL
 
 
+@pytest.mark.parametrize("d,n,cells", [(2, 64, 3), (3, 32, 2)])
+def test_error_stays_relative_to_q_close_to_equilibrium(gpu_lib, d, n, cells):
+    # g = f - M at 1e-3 of f: Q is of size |g| |f|, and plain FP32 leaves errors
+    # of size eps |f|^2 in it.  The mode keeps every complex transform either
+    # f-sized or g-sized, so the error stays at FP32 level relative to Q; a
+    # transform that packed a g-sized field with an f-sized one would give the
+    # g-sized field errors of size eps |f| and fail here.
+    f = _local_maxwellians(620 + d, d, n, cells, noise=1e-3)
+    plan = gpu_lib.Plan(d, n, 8.0, num_dirs=16, mode=NEAR)
+    q = _eval(plan, f)
+    errs = per_cell_rel_linf(q, oracle_near(plan, f), n ** d)
+    print("d=%d n=%d noise 1e-3: max cell rel err %.3e" % (d, n, errs.max()))
+    assert errs.max() <= TOL
+
+
 def test_far_from_equilibrium_still_exact_identity(gpu_lib):
     # the bilinear identity holds for every f: two separated Maxwellians
     f = workloads.two_maxwellians_batch(11, 6, 64, noise=0.05)
