@@ -258,7 +258,10 @@ __device__ __forceinline__ void jt_multiply(float2 (&z)[N], const HalfSpec<N, N 
     const lds_fptr lb = (lds_fptr)pb;
     float b0 = 0.f;
     if constexpr (BC) b0 = lb[0];
-    constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;   // spectrum loads in flight per chunk
+    // every spectrum load of the half row in flight at once: the transform's
+    // registers are free here, and one wait per job replaces one per chunk
+    // (chunks of 8 left the headline 4 % slower)
+    constexpr int C = N / 2 + 1;
 #pragma unroll
     for (int k0 = 0; k0 <= N / 2; k0 += C) {
         float2 F[C];
@@ -340,7 +343,7 @@ __device__ __forceinline__ void cell2d_eval(const DevPlan& pl, const Item2D& it,
             for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(z[i].x, z[i].y, acc[i]);
         } else {
             const float cw = gload(jobw, jb);
-            job2d_multiply<N, (N == 64 ? 0 : (N < 8 ? N : 8))>(z, fh, J, dtab, atab, j);
+            job2d_multiply<N, (N == 64 ? 64 : (N < 8 ? N : 8))>(z, fh, J, dtab, atab, j);
             inv2d<N, RV>(z, xb, j);
 #pragma unroll
             for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(cw * z[i].x, z[i].y, acc[i]);
@@ -445,7 +448,7 @@ __device__ __forceinline__ void cell2d_eval_bilinear(const DevPlan& pl, const It
                 const int mlane = (int)(threadIdx.x & 63) - j + ((N - j) & (N - 1));
                 RowWalk<N> am(atab + J.M * N, modc<N>((t ? sp : se) - (t ? dp : de)), modc<N>(-(t ? dp : de)));
                 RowWalk<N> bm(dtab + J.M * N, modc<N>((t ? se : sp) - (t ? de : dp)), modc<N>(-(t ? de : dp)));
-                constexpr int H = N / 2 + 1, CH = 8;
+                constexpr int H = N / 2 + 1, CH = H;   // every read of both half rows in flight at once
 #pragma unroll
                 for (int k0 = 0; k0 < H; k0 += CH) {
                     float2 G[CH], F[CH];
@@ -839,7 +842,7 @@ __device__ __forceinline__ void cell2d_eval_split_pair(const DevPlan& pl, const 
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
-        job2d_multiply<N, 8>(z, sp, J, dtab, atab, j);
+        job2d_multiply<N, 32>(z, sp, J, dtab, atab, j);
         __syncthreads();                         // the other wave has read this slot
         inv2d<N, RV>(z, own, j);
         wave_sync();
@@ -916,9 +919,10 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
     // R = Re(conj F(cf) fhat) on the own half row (written by this lane); the
     // reads of a chunk are issued before its stores, which the compiler cannot
     // tell apart from them
+    constexpr int CR = N / 2 + 1 < 17 ? N / 2 + 1 : 17;
 #pragma unroll
-    for (int k0 = 0; k0 <= N / 2; k0 += 8) {
-        constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;
+    for (int k0 = 0; k0 <= N / 2; k0 += CR) {
+        constexpr int C = CR;
         float2 F[C];
 #pragma unroll
         for (int i = 0; i < C; ++i)
@@ -970,7 +974,9 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
             RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * j), modc<N>(J.e[0]));
             RowWalk<N> am(atab + J.M * N, modc<N>(J.e[0] * j - J.e[1]), modc<N>(-J.e[1]));
             RowWalk<N> bm(dtab + J.M * N, modc<N>(-J.e[1] * j - J.e[0]), modc<N>(-J.e[0]));
-            constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;
+            // two chunks of reads at n = 64 (one chunk of 33 reads of F and R
+            // together would not leave the registers for two waves per SIMD)
+            constexpr int C = N / 2 + 1 < 17 ? N / 2 + 1 : 17;
 #pragma unroll
             for (int k0 = 0; k0 <= N / 2; k0 += C) {
                 float2 F[C];
@@ -1027,11 +1033,12 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
             const int jj = reread(j);
             RowWalk<N> a(atab + J.M * N, modc<N>(J.e[0] * jj), modc<N>(J.e[1]));
             RowWalk<N> b(dtab + J.M * N, modc<N>(-J.e[1] * jj), modc<N>(J.e[0]));
+            constexpr int CS = N / 2 + 1 < 8 ? N / 2 + 1 : 8;
 #pragma unroll
-            for (int k0 = 0; k0 <= N / 2; k0 += 8) {
+            for (int k0 = 0; k0 <= N / 2; k0 += CS) {
                 // the chunk's accumulator reads go out before its stores (the
                 // compiler would otherwise wait for each read in turn)
-                constexpr int C = N / 2 + 1 < 8 ? N / 2 + 1 : 8;
+                constexpr int C = CS;
                 float2 sv[C], m[C], w[C];
 #pragma unroll
                 for (int i = 0; i < C; ++i)
