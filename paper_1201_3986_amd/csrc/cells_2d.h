@@ -1021,7 +1021,9 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
                 const float c = bload(rc, vc, i * RS);
                 rpart = __builtin_fmaf(c * z[i].x, z[i].y, rpart);
                 z[i] = make_float2(c * z[i].y, c * z[i].x);   // c v + i c u
-                QDVM_CHUNK_FENCE(i);
+                // the cotangent's reads in flight 32 at a time (1.84 -> 1.80 ms
+                // at n = 64 against chunks of 8)
+                if ((i & 31) == 31) __builtin_amdgcn_sched_barrier(0);
             }
         }
         const float tot = group_sum<N>(rpart * inv_n2 - spart * inv_n);
