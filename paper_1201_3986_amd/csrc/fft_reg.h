@@ -207,93 +207,6 @@ struct DifStages<N, SIGN, L, R, Rs...> {
     }
 };
 
-// ------------------------------------------------- two-stage fused sweep
-// For N = R1 R2 the twiddles between the two DIF stages are applied inside the
-// first butterfly layer of the second stage's DFT: of a pair (a, b) with
-// twiddles (W^ta, W^tb), s = W^ta a + W^tb b is formed with the second twiddle
-// in FMAs and d = 2 W^ta a - s (the fused butterfly of Linzer and Feig,
-// "Implementation of efficient FFT algorithms on fused multiply-add
-// architectures", IEEE Trans. Signal Process. 41, 1993): two instructions fewer
-// per pair than a complex multiply followed by an add and a subtract, with the
-// same error to within 1 % against an FP64 DFT.
-template <int N, int SIGN>
-__host__ __device__ __forceinline__ void tw_pair(float2 a, int ta, float2 b, int tb, float2& s, float2& d)
-{
-    const float2 A = twiddle_mul<N, SIGN>(a, ta);
-    tb %= N;
-    if (tb == 0 || (4 * tb) % N == 0) {
-        const float2 B = twiddle_mul<N, SIGN>(b, tb);
-        s = cadd(A, B);
-        d = csub(A, B);
-        return;
-    }
-    const float c = kTw<N>.c[tb];
-    const float sn = SIGN > 0 ? kTw<N>.s[tb] : -kTw<N>.s[tb];
-    s.x = __builtin_fmaf(c, b.x, __builtin_fmaf(-sn, b.y, A.x));
-    s.y = __builtin_fmaf(c, b.y, __builtin_fmaf(sn, b.x, A.y));
-    d.x = __builtin_fmaf(2.f, A.x, -s.x);
-    d.y = __builtin_fmaf(2.f, A.y, -s.y);
-}
-// DFT of R points whose inputs still carry the twiddles W_N^t[i].
-template <int R, int N, int SIGN>
-struct DftTw;
-template <int N, int SIGN>
-struct DftTw<4, N, SIGN> {
-    static __host__ __device__ __forceinline__ void run(float2* y, const int* t)
-    {
-        float2 t0, t1, t2, t3;
-        tw_pair<N, SIGN>(y[0], t[0], y[2], t[2], t0, t1);
-        tw_pair<N, SIGN>(y[1], t[1], y[3], t[3], t2, t3);
-        t3 = mul_si<SIGN>(t3);
-        y[0] = cadd(t0, t2);
-        y[2] = csub(t0, t2);
-        y[1] = cadd(t1, t3);
-        y[3] = csub(t1, t3);
-    }
-};
-
-// Inputs 0 2 4 6 and 1 3 5 7 form two 4-point DFTs whose first layers pair
-// (0, 4), (2, 6) and (1, 5), (3, 7): those pairs take the fused twiddles.
-template <int N, int SIGN>
-struct DftTw<8, N, SIGN> {
-    static __host__ __device__ __forceinline__ void run(float2* y, const int* t)
-    {
-        constexpr float r2 = 0.70710678118654752f;
-        float2 e[4], o[4];
-        {
-            float2 t0, t1, t2, t3;
-            tw_pair<N, SIGN>(y[0], t[0], y[4], t[4], t0, t1);
-            tw_pair<N, SIGN>(y[2], t[2], y[6], t[6], t2, t3);
-            t3 = mul_si<SIGN>(t3);
-            e[0] = cadd(t0, t2);
-            e[2] = csub(t0, t2);
-            e[1] = cadd(t1, t3);
-            e[3] = csub(t1, t3);
-        }
-        {
-            float2 t0, t1, t2, t3;
-            tw_pair<N, SIGN>(y[1], t[1], y[5], t[5], t0, t1);
-            tw_pair<N, SIGN>(y[3], t[3], y[7], t[7], t2, t3);
-            t3 = mul_si<SIGN>(t3);
-            o[0] = cadd(t0, t2);
-            o[2] = csub(t0, t2);
-            o[1] = cadd(t1, t3);
-            o[3] = csub(t1, t3);
-        }
-        float2 o1 = make_float2(r2 * (o[1].x - SIGN * o[1].y), r2 * (o[1].y + SIGN * o[1].x));
-        float2 o2 = mul_si<SIGN>(o[2]);
-        float2 o3 = make_float2(r2 * (-o[3].x - SIGN * o[3].y), r2 * (-o[3].y + SIGN * o[3].x));
-        y[0] = cadd(e[0], o[0]);
-        y[4] = csub(e[0], o[0]);
-        y[1] = cadd(e[1], o1);
-        y[5] = csub(e[1], o1);
-        y[2] = cadd(e[2], o2);
-        y[6] = csub(e[2], o2);
-        y[3] = cadd(e[3], o3);
-        y[7] = csub(e[3], o3);
-    }
-};
-
 // position of spectral index k after the DIF sweep with radices Rs...
 template <int L, int... Rs>
 struct DigitRev {
@@ -322,43 +235,6 @@ __host__ __device__ __forceinline__ void fft_pencil(float2 (&x)[N])
     for (int k = 0; k < N; ++k) x[k] = t[k];
 }
 
-// Two-stage sweep N = R1 R2 (R2 in {4, 8}) with the inter-stage twiddles fused
-// into the second stage; natural order in and out.  Used at n = 64, where the
-// evaluation is bound by instruction issue (at n = 32 the 4 x 8 order of the 3D
-// kernels measured 1 % slower fused).
-template <int N, int SIGN, int R1, int R2>
-__host__ __device__ __forceinline__ void fft_pencil_fused(float2 (&x)[N])
-{
-    static_assert(R1 * R2 == N, "radices must multiply to N");
-#pragma unroll
-    for (int j = 0; j < R2; ++j) {
-        float2 y[R1];
-#pragma unroll
-        for (int n0 = 0; n0 < R1; ++n0) y[n0] = x[n0 * R2 + j];
-        Dft<R1, SIGN>::run(y);
-#pragma unroll
-        for (int k0 = 0; k0 < R1; ++k0) x[k0 * R2 + j] = y[k0];
-    }
-#pragma unroll
-    for (int k0 = 0; k0 < R1; ++k0) {
-        float2 y[R2];
-        int t[R2];
-#pragma unroll
-        for (int j = 0; j < R2; ++j) {
-            y[j] = x[k0 * R2 + j];
-            t[j] = j * k0;   // twiddle exponent left pending by the first stage
-        }
-        DftTw<R2, N, SIGN>::run(y, t);
-#pragma unroll
-        for (int k1 = 0; k1 < R2; ++k1) x[k0 * R2 + k1] = y[k1];
-    }
-    float2 tt[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) tt[k] = x[DigitRev<N, R1, R2>::pos(k)];
-#pragma unroll
-    for (int k = 0; k < N; ++k) x[k] = tt[k];
-}
-
 // Default radix choice per length (the autotuner may override).
 template <int N, int VARIANT>
 struct Radix;
@@ -370,7 +246,7 @@ template <> struct Radix<24, 0> { template <int S> static __host__ __device__ __
 template <> struct Radix<24, 1> { template <int S> static __host__ __device__ __forceinline__ void fft(float2 (&x)[24]) { fft_pencil<24, S, 3, 8>(x); } };
 template <> struct Radix<32, 0> { template <int S> static __host__ __device__ __forceinline__ void fft(float2 (&x)[32]) { fft_pencil<32, S, 8, 4>(x); } };
 template <> struct Radix<32, 1> { template <int S> static __host__ __device__ __forceinline__ void fft(float2 (&x)[32]) { fft_pencil<32, S, 4, 8>(x); } };
-template <> struct Radix<64, 0> { template <int S> static __host__ __device__ __forceinline__ void fft(float2 (&x)[64]) { fft_pencil_fused<64, S, 8, 8>(x); } };
+template <> struct Radix<64, 0> { template <int S> static __host__ __device__ __forceinline__ void fft(float2 (&x)[64]) { fft_pencil<64, S, 8, 8>(x); } };
 template <> struct Radix<64, 1> { template <int S> static __host__ __device__ __forceinline__ void fft(float2 (&x)[64]) { fft_pencil<64, S, 4, 4, 4>(x); } };
 
 }  // namespace qdvm
