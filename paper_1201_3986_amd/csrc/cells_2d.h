@@ -842,7 +842,7 @@ __device__ __forceinline__ void cell2d_eval_split_pair(const DevPlan& pl, const 
     for (int jb = 0; jb < pl.njobs; ++jb) {
         const JobDesc J = gload(pl.jobs, jb);
         const float cw = gload(jobw, jb);
-        job2d_multiply<N, 32>(z, sp, J, dtab, atab, j);
+        job2d_multiply<N, 64>(z, sp, J, dtab, atab, j);   // the whole row's reads in flight at once
         __syncthreads();                         // the other wave has read this slot
         inv2d<N, RV>(z, own, j);
         wave_sync();
