@@ -1026,7 +1026,8 @@ __device__ __forceinline__ void cell2d_vjp(const DevPlan& pl, const Item2D& it, 
                 if ((i & 31) == 31) __builtin_amdgcn_sched_barrier(0);
             }
         }
-        const float tot = group_sum<N>(rpart * inv_n2 - spart * inv_n);
+        // FP64 across the cell's lanes: the per-lane terms largely cancel
+        const double tot = group_sumd<N>((double)rpart * inv_n2 - (double)spart * inv_n);
         if (j == 0 && valid) gw_accumulate(gwp + jb, tot, gw_first);
         fwd2d<N, RV>(z, xb, j);
         {

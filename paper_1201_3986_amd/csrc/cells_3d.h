@@ -156,31 +156,18 @@ __device__ __forceinline__ void inv3d(float2 (&z)[Q][N], float* xb, int tid)
     for (int q = 0; q < Q; ++q) fftp<N, RV, 1>(z[q]);
 }
 
-// Sum over the 64 lanes of a wave (uniform result): xor swizzles within each
-// half, then the two halves.  Nothing lane-dependent stays live between calls.
-__device__ __forceinline__ float wave_sum(float v)
+// FP64 sum over the workgroup (uniform result), for the grad_w partials: one
+// cell's partial adds 1024 lanes' terms that largely cancel, and an FP32 tree
+// over them leaves ~1e-5 of the result.  red: 8-byte aligned, one double per wave.
+template <int T>
+__device__ __forceinline__ double block_sumd(double v, double* red, int tid)
 {
-#define QDVM_SWZ_ADD(pat) \
-    v += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), pat))
-    QDVM_SWZ_ADD(0x041F);   // and 0x1f, xor 1
-    QDVM_SWZ_ADD(0x081F);   // xor 2
-    QDVM_SWZ_ADD(0x101F);   // xor 4
-    QDVM_SWZ_ADD(0x201F);   // xor 8
-    QDVM_SWZ_ADD(0x401F);   // xor 16
-#undef QDVM_SWZ_ADD
-    const int a = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0);
-    const int b = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32);
-    return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
-}
-
-template <int N, int T, int Q>
-__device__ __forceinline__ float block_sum(float v, float* red, int tid)
-{
-    v = wave_sum(v);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    float t = 0.f;
+    double t = 0.0;
 #pragma unroll
     for (int w = 0; w < (T + 63) / 64; ++w) t += red[w];
     return t;
@@ -1003,7 +990,8 @@ __device__ __forceinline__ void cell3d_vjp(const DevPlan& pl, const Cell3D& cl, 
                 if ((x & 15) == 15) __builtin_amdgcn_sched_barrier(0);
             }
         }
-        const float tot = block_sum<N, T, Q>(rpart * inv_n2 - spart * inv_n, red, tid);
+        const double tot = block_sumd<T>((double)rpart * inv_n2 - (double)spart * inv_n,
+                                         reinterpret_cast<double*>(red), tid);
         if (tid == 0) gw_accumulate(gwp + jb, tot, gw_first);
         fwd3d<N, T, Q, RV>(z, xb, tid);
         // Only the Hermitian part of (a - i a') uhat reaches Re IFFT(S), so S is

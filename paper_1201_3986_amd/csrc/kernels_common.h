@@ -183,12 +183,12 @@ __device__ __forceinline__ double opaque(double v)
 // fixed order, so the sum is the same on every run; the add is an atomic
 // read-modify-write performed at the device-coherent cache level, which cannot
 // see a stale copy of the value this thread wrote before.
-__device__ __forceinline__ void gw_accumulate(double* p, float v, bool first)
+__device__ __forceinline__ void gw_accumulate(double* p, double v, bool first)
 {
     if (first)
-        *p = (double)v;
+        *p = v;
     else
-        atomicAdd(p, (double)v);
+        atomicAdd(p, v);
 }
 
 template <int N>
@@ -206,15 +206,6 @@ __device__ __forceinline__ void fftp(float2 (&x)[N])
     __builtin_amdgcn_sched_barrier(0);
     Radix<N, RV>::template fft<SIGN>(x);
     __builtin_amdgcn_sched_barrier(0);
-}
-
-// Sum over the n lanes of an aligned lane group.
-template <int N>
-__device__ __forceinline__ float group_sum(float v)
-{
-#pragma unroll
-    for (int o = N / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
 }
 
 

@@ -40,6 +40,27 @@ def test_vjp_small(gpu_lib, d, n, P, batch):
     assert ef <= TOL and ew <= TOL
 
 
+@pytest.mark.parametrize("d,n,P,batch", [(2, 64, 2, 3), (2, 16, 1, 5), (3, 32, 1, 1), (3, 24, 1, 2)])
+def test_vjp_single_job(gpu_lib, d, n, P, batch):
+    # one job: the accumulator's first job is also its last (read and written
+    # through the empty descriptor, its sums kept for the final transform); at
+    # 3D n = 32 the single cell's directions are split over workgroups, all but
+    # one of which hold no job
+    import torch
+    rng = np.random.default_rng(7 * n + P)
+    f = workloads.random_positive(300 + n, d, n, batch)
+    c = rng.standard_normal(f.shape).astype(np.float32)
+    plan = gpu_lib.Plan(d, n, 8.0, num_dirs=P)
+    assert plan.num_jobs == 1
+    gf, gw = plan.vjp(_dev(f), _dev(c))
+    torch.cuda.synchronize()
+    rf, rw = oracle_vjp(plan, f, c)
+    ef = rel_linf(gf.cpu().numpy(), rf)
+    ew = rel_linf(gw.cpu().numpy(), rw)
+    print("single-job vjp d=%d n=%d P=%d batch=%d: grad_f %.3e grad_w %.3e" % (d, n, P, batch, ef, ew))
+    assert ef <= TOL and ew <= TOL
+
+
 def test_vjp_call_weights_and_determinism(gpu_lib):
     import torch
     rng = np.random.default_rng(3)
