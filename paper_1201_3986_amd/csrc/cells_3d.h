@@ -158,12 +158,40 @@ __device__ __forceinline__ void inv3d(float2 (&z)[Q][N], float* xb, int tid)
 
 // FP64 sum over the workgroup (uniform result), for the grad_w partials: one
 // cell's partial adds 1024 lanes' terms that largely cancel, and an FP32 tree
-// over them leaves ~1e-5 of the result.  red: 8-byte aligned, one double per wave.
+// over them leaves ~1e-5 of the result (2e-5 measured for a single direction at
+// n = 32, 3e-7 in FP64).  red: 8-byte aligned, one double per wave.  The wave
+// sums use swizzles, not lane shuffles: an FP64 shuffle chain on this per-job
+// path made the adjoint of 64 n = 32 cells 8 % slower.
+// FP64 sum over the 64 lanes of a wave (uniform result): xor swizzles of the two
+// 32-bit halves within each half-wave, then the two half-waves by readlane.
+__device__ __forceinline__ double wave_sumd(double v)
+{
+#define QDVM_SWZ_ADDD(pat)                                                                        \
+    do {                                                                                          \
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);                   \
+        const unsigned lo = (unsigned)__builtin_amdgcn_ds_swizzle((int)(unsigned)b, pat);         \
+        const unsigned hi = (unsigned)__builtin_amdgcn_ds_swizzle((int)(unsigned)(b >> 32), pat); \
+        v += __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);                    \
+    } while (0)
+    QDVM_SWZ_ADDD(0x041F);   // and 0x1f, xor 1
+    QDVM_SWZ_ADDD(0x081F);   // xor 2
+    QDVM_SWZ_ADDD(0x101F);   // xor 4
+    QDVM_SWZ_ADDD(0x201F);   // xor 8
+    QDVM_SWZ_ADDD(0x401F);   // xor 16
+#undef QDVM_SWZ_ADDD
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned a0 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 0);
+    const unsigned a1 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 0);
+    const unsigned c0 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 32);
+    const unsigned c1 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 32);
+    return __builtin_bit_cast(double, ((unsigned long long)a1 << 32) | a0) +
+           __builtin_bit_cast(double, ((unsigned long long)c1 << 32) | c0);
+}
+
 template <int T>
 __device__ __forceinline__ double block_sumd(double v, double* red, int tid)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    v = wave_sumd(v);
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
